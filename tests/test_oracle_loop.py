@@ -1,0 +1,120 @@
+"""Pins of the oracle's coupled time loop: plasma oscillation, energy drift, forms."""
+import math
+
+import numpy as np
+import pytest
+
+import inputs
+from oracle import physics as ph
+from oracle.pic import FP32, FP64, Grid, Species, to_fp32_state
+from oracle.sim import Sim
+
+
+def cold_plasma(wdt, gather, N=128, ppc=8, n0=1e15, amp=0.01):
+    """Periodic box, cold electrons at cell centres displaced by
+    amp dx sin(2 pi x / L), neutralising background."""
+    wpe = math.sqrt(n0 * ph.QE ** 2 / (ph.EPS0 * ph.ME))
+    L = 0.01
+    dx = L / N
+    n = N * ppc
+    x0 = (np.arange(n) + 0.5) * (L / n)
+    x = x0 + amp * dx * np.sin(2 * math.pi * x0 / L)
+    z = np.zeros(n)
+    sp = Species(s=0, prec=FP64, vx=z.copy(), vy=z.copy(), vz=z.copy(),
+                 id=np.arange(n, dtype=np.uint64), knext=np.full(n, 2 ** 31 - 1, np.int64), x=x)
+    cfg = inputs.small_discharge(n_cells=N, bc=1, gap_m=L, v_rf=0.0, n0_m3=n0, n_per_species=n,
+                                 dt_s=wdt / wpe, gather=gather, n_species=1, collisions=0)
+    return Sim(cfg, species=[sp]), wpe
+
+
+def measured_frequency(series, dt):
+    s = np.asarray(series) - np.mean(series)
+    idx = np.nonzero(np.signbit(s[:-1]) != np.signbit(s[1:]))[0]
+    t = [(i + s[i] / (s[i] - s[i + 1])) * dt for i in idx]
+    half_periods = len(t) - 1
+    return math.pi * half_periods / (t[-1] - t[0])
+
+
+@pytest.mark.parametrize("wdt", [0.05, 0.1])
+@pytest.mark.parametrize("gather", [0, 1])
+def test_cold_plasma_oscillation_frequency(wdt, gather):
+    sim, wpe = cold_plasma(wdt, gather)
+    dt = sim.dt
+    L = sim.L
+    nsteps = int(round(8 * 2 * math.pi / wdt))
+    amp = []
+    N = sim.grid.N
+    # A sin(2 pi x/L) displacement perturbs the charge as cos(2 pi x/L).
+    basis = np.cos(2 * math.pi * sim.grid.nodes[:N] / L)
+    for _ in range(nsteps):
+        sim.step()
+        amp.append(float(np.sum(sim.Q[:N] * basis)))
+    w = measured_frequency(amp, dt)
+    expect = (2 / dt) * math.asin(wpe * dt / 2)
+    assert abs(w / expect - 1) < 0.005
+
+
+def thermal_periodic(gather, wdt, seed, ncell=32, ppc=64, dx_over_ld=4.0):
+    n0, te = 1e15, 2.0
+    ld = math.sqrt(ph.EPS0 * te / (n0 * ph.QE))
+    wpe = math.sqrt(n0 * ph.QE ** 2 / (ph.EPS0 * ph.ME))
+    cfg = inputs.small_discharge(n_cells=ncell, bc=1, gap_m=ncell * dx_over_ld * ld, v_rf=0.0,
+                                 n0_m3=n0, te_ev=te, n_per_species=ncell * ppc, dt_s=wdt / wpe,
+                                 gather=gather, n_species=1, collisions=0, seed=seed, pullback=1)
+    return Sim(cfg)
+
+
+def energy_slope(gather, wdt, seed, t_wpe=400.0):
+    sim = thermal_periodic(gather, wdt, seed)
+    n = int(round(t_wpe / wdt))
+    ke_prev = sim.kinetic_energy(0)
+    tot = []
+    for _ in range(n):
+        sim.step()
+        ke = sim.kinetic_energy(0)
+        tot.append(0.5 * (ke_prev + ke) + sim.field_energy)
+        ke_prev = ke
+    tot = np.array(tot) / tot[0]
+    return np.polyfit(np.arange(n) * wdt, tot, 1)[0]
+
+
+@pytest.mark.slow
+def test_ec_energy_drift_scales_as_dt_squared_and_mc_heats():
+    """Section 1 / Appendix B: EC-PIC bounds energy growth (drift ~ dt^2) while
+    MC-PIC at dx = 4 lambda_De heats by the finite-grid instability."""
+    wdts = [0.4, 0.2, 0.1]
+    slopes = [np.mean([energy_slope(0, w, s) for s in range(4)]) for w in wdts]
+    assert all(s > 0 for s in slopes)
+    p = np.polyfit(np.log(wdts), np.log(slopes), 1)[0]
+    assert 1.5 <= p <= 2.5
+    mc = np.mean([energy_slope(1, 0.1, s) for s in range(2)])
+    assert mc > 10 * slopes[-1]
+
+
+def test_fp32_form_tracks_fp64_form_for_one_step():
+    """A single step from the same state (FP32 state widened exactly to FP64)
+    agrees between the two forms to 1e-5."""
+    cfg = inputs.small_discharge(n_per_species=4000, seed=3, precision=FP32, gamma_see=0.0)
+    s32 = Sim(cfg)
+    s32.run(3)
+    sps64 = []
+    for sp in s32.sp:
+        sps64.append(Species(s=sp.s, prec=FP64, vx=sp.vx.astype(np.float64),
+                             vy=sp.vy.astype(np.float64), vz=sp.vz.astype(np.float64),
+                             id=sp.id.copy(), knext=sp.knext.copy(),
+                             x=s32.grid.position(sp.cell, sp.off)))
+    cfg64 = dict(cfg, precision=FP64)
+    s64 = Sim(cfg64, species=sps64, k=s32.k)
+    s32.step()
+    s64.step()
+    for a, b in zip(s32.sp, s64.sp):
+        ai, bi = a.order_by_id(), b.order_by_id()
+        common = np.intersect1d(ai.id, bi.id)
+        assert len(common) >= 0.999 * min(ai.n, bi.n)
+        ma = np.isin(ai.id, common)
+        mb = np.isin(bi.id, common)
+        xa = s32.grid.position(ai.cell[ma], ai.off[ma])
+        assert np.max(np.abs(xa - bi.x[mb])) < 1e-5 * s32.L
+        vs = np.max(np.abs(bi.vx[mb])) + 1.0
+        assert np.max(np.abs(ai.vx[ma].astype(np.float64) - bi.vx[mb])) < 1e-5 * vs
+    assert np.max(np.abs(s32.phi - s64.phi)) < 1e-5 * np.max(np.abs(s64.phi))
