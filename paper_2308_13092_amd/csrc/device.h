@@ -1,0 +1,174 @@
+// device.h -- data layout and device helpers of the EC-PIC kernels (gfx950).
+//
+// Layout in HBM (all inside the caller's arena):
+//   InstDev[n_inst]    read-only parameters and array pointers of every slot
+//   InstState[n_inst]  step index, particle extents, sticky status, counters
+//   per slot: a grid block (nodes, widths, walk tables, deposits, potential,
+//             fields, averaging accumulators, sort counters) and, per species,
+//             two particle buffers (the cell sort ping-pongs between them).
+// Particles are stored as structure-of-arrays, each field a contiguous array
+// of `cap` elements (cap is a multiple of 64, so every array is 256-B
+// aligned):
+//   FP32-state form: cell i32 | off f32 | vx f32 | vy f32 | vz f32 | knext i32 | id u64
+//   FP64 form:       x f64    | vx f64  | vy f64 | vz f64 | knext i32 | id u64
+// A dead (absorbed) particle keeps its slot until the next sort with
+// cell = -1 (FP32) or x = -1 (FP64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ecpic {
+
+// CODATA 2018 (e and k_B exact in the 2019 SI).
+constexpr double kQE = 1.602176634e-19;
+constexpr double kME = 9.1093837015e-31;
+constexpr double kAMU = 1.66053906660e-27;
+constexpr double kEPS0 = 8.8541878128e-12;
+constexpr double kKB = 1.380649e-23;
+constexpr double kMAR = 39.948 * kAMU;
+constexpr double kTWO_PI = 2.0 * 3.14159265358979323846;
+constexpr double kEXC = 11.5;     // eV, excitation threshold
+constexpr double kION = 15.76;    // eV, ionisation threshold
+constexpr double kSIGMA_CX = 5.0e-19;
+constexpr int32_t kINT32_MAX = 2147483647;
+
+constexpr int kMaxInst = 512;
+constexpr int kMaxCells = 2048;
+constexpr int kNctr = 24;
+
+// Philox counter tags (counter word 1 = tag | species << 8).
+enum : uint32_t {
+  TAG_COLL = 0, TAG_EJECT = 1, TAG_GAS = 2, TAG_SEE = 3, TAG_CHILD = 4, TAG_SEE_POS = 5,
+  TAG_SKIP = 7, TAG_INIT0 = 0xF0, TAG_INIT1 = 0xF1
+};
+
+// Cumulative counters in InstState::ctr.
+enum : int {
+  C_PSTEPS = 0, C_ABS = 1,            // C_ABS + 2*species + wall (wall 0 left, 1 right)
+  C_EABS = 5,                         // absorbed energy, 2^-16 eV units, same indexing
+  C_SEE = 9, C_IZ = 10, C_EX = 11, C_EL = 12, C_CX = 13, C_CAND = 14,   // C_CAND + species
+  C_BOUND = 16, C_NONFINITE = 17
+};
+
+enum : int { ST_CAPACITY = 1, ST_NONFINITE = 2, ST_GROWTH = 4 };
+
+struct InstDev {
+  int32_t active, N, bc, gather;
+  int32_t nsp, uniform, collisions, eedf_bins;
+  int32_t avg_every, eedf_every, int_path, pad0;
+  int64_t avg_start, k_stop;
+  int64_t cap[2];
+  int64_t n_init[2];
+  double L, dx, dt, hmin;
+  double v_rf, w_rf, phase, growth_limit;
+  double n_g, vti, vt_see, gamma_see;
+  double nu_max[2], nudt[2], qmdt[2], qW[2], hq[2], mass[2];
+  double W, cgauss;
+  double eedf_de, eedf_centre, eedf_half, pad1;
+  float qmdt32[2], hq32[2];
+  float dtoh32u, pad2[3];
+  uint64_t seed;
+  // grid block
+  double *nodes, *h, *V;
+  float *dtoh32, *rf32, *rb32;
+  int64_t *A[2][2];            // [k parity][species]
+  double *phi, *E64;
+  float *E32;
+  double *accA[2], *acc_phi;
+  unsigned long long *eedf;
+  unsigned long long *scount[2], *scursor[2];
+  // particles
+  char *pbuf[2][2];            // [species][buffer]
+};
+
+struct InstState {
+  int64_t k;
+  int32_t status, parity;
+  int32_t frozen, pad0;
+  int64_t extent[2];
+  unsigned long long append[2];
+  unsigned long long step_live[2];
+  unsigned long long step_absorbed[2];
+  int64_t n_live[2];
+  unsigned long long ctr[kNctr];
+  double field_energy, ne_max;
+  int32_t n_samples, eedf_samples;
+  int64_t sort_live[2];
+};
+
+// ---------------------------------------------------------------------------
+// Particle buffer views
+// ---------------------------------------------------------------------------
+struct P32 {
+  int32_t *cell; float *off, *vx, *vy, *vz; int32_t *knext; uint64_t *id;
+};
+struct P64 {
+  double *x, *vx, *vy, *vz; int32_t *knext; uint64_t *id;
+};
+__host__ __device__ inline P32 view32(char *b, int64_t cap) {
+  P32 p;
+  p.cell = reinterpret_cast<int32_t *>(b);
+  p.off = reinterpret_cast<float *>(b + 4 * cap);
+  p.vx = reinterpret_cast<float *>(b + 8 * cap);
+  p.vy = reinterpret_cast<float *>(b + 12 * cap);
+  p.vz = reinterpret_cast<float *>(b + 16 * cap);
+  p.knext = reinterpret_cast<int32_t *>(b + 20 * cap);
+  p.id = reinterpret_cast<uint64_t *>(b + 24 * cap);
+  return p;
+}
+__host__ __device__ inline P64 view64(char *b, int64_t cap) {
+  P64 p;
+  p.x = reinterpret_cast<double *>(b);
+  p.vx = reinterpret_cast<double *>(b + 8 * cap);
+  p.vy = reinterpret_cast<double *>(b + 16 * cap);
+  p.vz = reinterpret_cast<double *>(b + 24 * cap);
+  p.knext = reinterpret_cast<int32_t *>(b + 32 * cap);
+  p.id = reinterpret_cast<uint64_t *>(b + 36 * cap);
+  return p;
+}
+constexpr int64_t kBytes32 = 32, kBytes64 = 44;
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11) and the uniform / normal variates.
+// key = particle id, counter = (k, tag | species << 8, seed_lo, seed_hi).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox(uint32_t k, uint32_t tag, uint64_t seed, uint64_t id) {
+  uint32_t c0 = k, c1 = tag, c2 = (uint32_t)seed, c3 = (uint32_t)(seed >> 32);
+  uint32_t k0 = (uint32_t)id, k1 = (uint32_t)(id >> 32);
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
+  }
+  return make_uint4(c0, c1, c2, c3);
+}
+
+__device__ __forceinline__ double u32d(uint32_t r) { return ((double)r + 0.5) * 0x1p-32; }
+__device__ __forceinline__ double u52d(uint32_t a, uint32_t b) {
+  const uint64_t m = ((uint64_t)a << 20) | (uint64_t)(b >> 12);
+  return ((double)m + 0.5) * 0x1p-52;
+}
+__device__ __forceinline__ void box_muller(double ua, double ub, double &z0, double &z1) {
+  const double r = sqrt(-2.0 * log(ua));
+  const double a = kTWO_PI * ub;
+  z0 = r * cos(a);
+  z1 = r * sin(a);
+}
+// First candidate step after `base - 1`: base + floor(-ln u / (nu_max dt)).
+__device__ __forceinline__ int32_t geometric(double base, double u, double nudt) {
+  double g = floor(-log(u) / nudt);
+  g = fmin(g, (double)kINT32_MAX);
+  const double out = fmin(base + g, (double)kINT32_MAX);
+  return (int32_t)out;
+}
+__device__ __forceinline__ int32_t next_candidate(uint64_t id, int64_t k, int s, uint64_t seed,
+                                                  double nudt) {
+  if (!(nudt > 0.0)) return kINT32_MAX;
+  const uint4 r = philox((uint32_t)k, TAG_SKIP | (uint32_t)(s << 8), seed, id);
+  return geometric((double)(k + 1), u52d(r.x, r.y), nudt);
+}
+
+}  // namespace ecpic

@@ -1,0 +1,31 @@
+// kernels.h -- host-side launchers of the EC-PIC kernels (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+
+namespace ecpic {
+
+enum Mode : int { M_DEPOSIT = 0, M_PUSH = 1, M_MCC = 2, M_FUSED = 3, M_PULLBACK = 4 };
+
+// Dynamic LDS bytes of the particle kernels for grids of up to max_n cells.
+size_t particle_lds_bytes(int prec, int max_n);
+size_t sort_lds_bytes(int max_n);
+
+void launch_field(const InstDev *insts, InstState *states, int n_inst, int mode, hipStream_t s);
+void launch_init(const InstDev *insts, InstState *states, int inst, int species, int prec,
+                 double t_ev, int64_t n, hipStream_t s);
+// Persistent pass over every particle of every active instance.
+hipError_t launch_particles(const InstDev *insts, InstState *states, int n_inst, int prec,
+                            int mode, int block, int grid, int max_n, unsigned int *done,
+                            hipStream_t s);
+hipError_t launch_sort(const InstDev *insts, InstState *states, int n_inst, int prec, int grid,
+                       int max_n, unsigned int *done, hipStream_t s);
+void launch_diag(const InstDev *insts, InstState *states, int inst, int prec,
+                 unsigned long long *out, hipStream_t s);
+void launch_zero_deposit(const InstDev *insts, InstState *states, int n_inst, hipStream_t s);
+
+// Diagnostics reduction output layout (unsigned long long words).
+enum : int { D_LIVE0 = 0, D_LIVE1 = 1, D_KE0 = 2, D_KE1 = 3, D_VMAX = 4, D_NWORDS = 8 };
+
+}  // namespace ecpic

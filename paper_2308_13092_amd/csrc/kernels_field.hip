@@ -1,0 +1,210 @@
+// kernels_field.hip -- Poisson solve and field of every instance (Eqs 4-5).
+//
+// One workgroup per instance.  The paper solves the 3-point Poisson system by
+// LU decomposition (Section 2), a sequential sweep of ~2N dependent steps.
+// Here the same finite-volume system
+//   (phi_{n+1}-phi_n)/h_n - (phi_n-phi_{n-1})/h_{n-1} = -Q_n/eps0,  n = 1..N-1
+// is solved in its equivalent Gauss-law form, which is parallel:
+//   E_j - E_{j-1} = Q_j/eps0   =>   E_j = E_0 + G_j,  G_j = (1/eps0) sum_{n=1..j} Q_n,
+//   sum_j h_j E_j = phi_0 - phi_N fixes E_0,  phi_j = phi_0 - sum_{i<j} h_i E_i.
+// When both species carry the same |q| W (or only electrons move), the charge
+// prefix is an exact int64 prefix of the fixed-point deposit, so G_j takes a
+// single rounding.  All prefix sums and reductions use a fixed blocking, so
+// the result is bit-reproducible.
+#include "device.h"
+#include "kernels.h"
+
+namespace ecpic {
+
+constexpr int kFB = 256;  // threads per field workgroup
+
+template <typename T>
+__device__ void block_scan_inclusive(T *a, int n, T *tmp) {
+  const int t = threadIdx.x;
+  const int c = (n + kFB - 1) / kFB;
+  const int lo = min(n, t * c), hi = min(n, lo + c);
+  T s = T(0);
+  for (int i = lo; i < hi; ++i) { s += a[i]; a[i] = s; }
+  tmp[t] = s;
+  __syncthreads();
+  for (int off = 1; off < kFB; off <<= 1) {
+    const T v = (t >= off) ? tmp[t - off] : T(0);
+    __syncthreads();
+    tmp[t] += v;
+    __syncthreads();
+  }
+  const T base = (t > 0) ? tmp[t - 1] : T(0);
+  for (int i = lo; i < hi; ++i) a[i] += base;
+  __syncthreads();
+}
+
+template <typename T>
+__device__ T block_sum(T v, T *tmp) {
+  const int t = threadIdx.x;
+  tmp[t] = v;
+  __syncthreads();
+  for (int off = kFB / 2; off > 0; off >>= 1) {
+    if (t < off) tmp[t] += tmp[t + off];
+    __syncthreads();
+  }
+  const T r = tmp[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ double block_max(double v, double *tmp) {
+  const int t = threadIdx.x;
+  tmp[t] = v;
+  __syncthreads();
+  for (int off = kFB / 2; off > 0; off >>= 1) {
+    if (t < off) tmp[t] = fmax(tmp[t], tmp[t + off]);
+    __syncthreads();
+  }
+  const double r = tmp[0];
+  __syncthreads();
+  return r;
+}
+
+// mode bit 0: accumulate the averaged profiles when due; bit 1: zero the
+// deposit buffer of step k+1 (for the fused particle pass).
+__global__ void __launch_bounds__(kFB)
+k_field(const InstDev *__restrict__ insts, InstState *__restrict__ states, int mode) {
+  __shared__ int64_t sA[2][kMaxCells + 1];
+  __shared__ double sG[kMaxCells + 1];
+  __shared__ double sE[kMaxCells + 1];
+  __shared__ double sQ[kMaxCells + 1];
+  __shared__ int64_t sD[kMaxCells + 1];
+  __shared__ int64_t tmpi[kFB];
+  __shared__ double tmpd[kFB];
+
+  const InstDev &I = insts[blockIdx.x];
+  InstState &S = states[blockIdx.x];
+  if (!I.active || S.frozen != 0) return;
+  if (I.k_stop > 0 && S.k >= I.k_stop) return;
+  const int t = threadIdx.x;
+  const int N = I.N;
+  const int64_t k = S.k;
+  const int par = (int)(k & 1);
+  const bool periodic = I.bc == 1;
+  const int nsp = I.nsp;
+
+  for (int n = t; n <= N; n += kFB) {
+    sA[0][n] = I.A[par][0][n];
+    sA[1][n] = (nsp > 1) ? I.A[par][1][n] : 0;
+  }
+  __syncthreads();
+  // Q_n = sum_s (q_s W A_{s,n}) 2^-32.
+  for (int n = t; n <= N; n += kFB) {
+    double q = (I.qW[0] * (double)sA[0][n]) * 0x1p-32;
+    if (nsp > 1) q = q + (I.qW[1] * (double)sA[1][n]) * 0x1p-32;
+    sQ[n] = q;
+  }
+  __syncthreads();
+  const double t_k = (double)k * I.dt;
+  const double phi0 = periodic ? 0.0 : I.v_rf * sin(I.w_rf * t_k + I.phase);
+  const double phiN = 0.0;
+
+  // G_j, j = 0..N-1 (G_0 = 0).
+  if (!periodic && I.int_path) {
+    for (int n = t; n < N; n += kFB)
+      sD[n] = (n == 0) ? 0 : ((nsp > 1) ? (sA[1][n] - sA[0][n]) : sA[0][n]);
+    __syncthreads();
+    block_scan_inclusive<int64_t>(sD, N, tmpi);
+    for (int n = t; n < N; n += kFB) sG[n] = I.cgauss * (double)sD[n];
+    __syncthreads();
+  } else {
+    double qbg = 0.0;
+    if (periodic) {
+      double part = 0.0;
+      for (int n = t; n < N; n += kFB) part += sQ[n];
+      qbg = block_sum<double>(part, tmpd) / I.L;
+    }
+    for (int n = t; n < N; n += kFB) {
+      const double qn = periodic ? (sQ[n] - qbg * I.V[n]) : sQ[n];
+      sG[n] = (n == 0) ? 0.0 : qn / kEPS0;
+    }
+    __syncthreads();
+    block_scan_inclusive<double>(sG, N, tmpd);
+  }
+
+  // E_0 from sum_j h_j E_j = phi_0 - phi_N.
+  double part = 0.0;
+  for (int j = t; j < N; j += kFB) part += I.h[j] * sG[j];
+  const double hg = block_sum<double>(part, tmpd);
+  const double e0 = (phi0 - phiN - hg) / I.L;
+  for (int j = t; j < N; j += kFB) sE[j] = e0 + sG[j];
+  __syncthreads();
+
+  // phi_j = phi_0 - sum_{i<j} h_i E_i  (reuse sG for the prefix).
+  for (int j = t; j < N; j += kFB) sG[j] = I.h[j] * sE[j];
+  __syncthreads();
+  block_scan_inclusive<double>(sG, N, tmpd);
+  for (int n = t; n <= N; n += kFB) {
+    double p;
+    if (n == 0) p = phi0;
+    else if (n == N) p = phiN;
+    else p = phi0 - sG[n - 1];
+    I.phi[n] = p;
+  }
+
+  // Field handed to the particles.
+  if (I.gather == 0) {
+    for (int j = t; j < N; j += kFB) {
+      I.E64[j] = sE[j];
+      I.E32[j] = (float)sE[j];
+    }
+  } else {
+    for (int n = t; n <= N; n += kFB) {
+      double en;
+      if (n > 0 && n < N) {
+        en = (I.h[n - 1] * sE[n - 1] + I.h[n] * sE[n]) / (I.h[n - 1] + I.h[n]);
+      } else if (periodic) {
+        en = (I.h[N - 1] * sE[N - 1] + I.h[0] * sE[0]) / (I.h[N - 1] + I.h[0]);
+      } else if (n == 0) {
+        en = sE[0] - sQ[0] / kEPS0;
+      } else {
+        en = sE[N - 1] + sQ[N] / kEPS0;
+      }
+      I.E64[n] = en;
+      I.E32[n] = (float)en;
+    }
+  }
+
+  // Field energy and the density maximum (stability monitor 1b).
+  double fe = 0.0;
+  for (int j = t; j < N; j += kFB) fe += I.h[j] * sE[j] * sE[j];
+  fe = block_sum<double>(fe, tmpd);
+  double nm = 0.0;
+  for (int n = t; n <= N; n += kFB) nm = fmax(nm, ((double)sA[0][n] * I.W * 0x1p-32) / I.V[n]);
+  nm = block_max(nm, tmpd);
+  if (t == 0) {
+    S.field_energy = 0.5 * kEPS0 * fe;
+    S.ne_max = nm;
+  }
+
+  // RF-averaged profiles (Section 3a).
+  if ((mode & 1) && I.avg_every > 0 && k >= I.avg_start && ((k - I.avg_start) % I.avg_every) == 0) {
+    for (int n = t; n <= N; n += kFB) {
+      I.accA[0][n] += (double)sA[0][n];
+      if (nsp > 1) I.accA[1][n] += (double)sA[1][n];
+      I.acc_phi[n] += (n == 0) ? phi0 : ((n == N) ? phiN : phi0 - sG[n - 1]);
+    }
+    if (t == 0) S.n_samples += 1;
+  }
+  if ((mode & 1) && t == 0 && I.eedf_every > 0 && k >= I.avg_start &&
+      ((k - I.avg_start) % I.eedf_every) == 0)
+    S.eedf_samples += 1;
+  // Clear the deposit of step k+1 for the fused particle pass.
+  if (mode & 2) {
+    for (int n = t; n <= N; n += kFB) {
+      I.A[par ^ 1][0][n] = 0;
+      if (nsp > 1) I.A[par ^ 1][1][n] = 0;
+    }
+  }
+}
+
+void launch_field(const InstDev *insts, InstState *states, int n_inst, int mode, hipStream_t s) {
+  hipLaunchKernelGGL(k_field, dim3(n_inst), dim3(kFB), 0, s, insts, states, mode);
+}
+
+}  // namespace ecpic

@@ -1,0 +1,1092 @@
+// kernels_particles.hip -- the particle side of the EC-PIC step on gfx950.
+//
+// One persistent kernel template serves every particle pass.  The grid is a
+// fixed number of workgroups (a multiple of the CU count); each workgroup
+// takes an equal contiguous range of 4*BLOCK-particle tiles of the
+// concatenated (instance, species) segments, so any number of instances of
+// any size advance in one launch.  Per tile a thread owns 4 consecutive
+// particles and reads them with 16-byte vector loads, so a wavefront streams
+// 1 KB of each state array per instruction.
+//
+// Modes:
+//   M_DEPOSIT   Eqs 2-3: fixed-point CIC weights of x^k into the LDS copy of
+//               the node deposit, flushed to HBM with int64 atomics.
+//   M_PUSH      Eqs 6-9: gather E^k, leapfrog, absorption at the electrodes,
+//               secondary emission, central EEDF sample.
+//   M_MCC       step 6: null collisions of the particles due this step,
+//               ionisation pairs appended, then k <- k+1.
+//   M_FUSED     M_PUSH + M_MCC + the deposit of x^{k+1}, in one pass.
+//   M_PULLBACK  v^{-1/2} = v^0 - (q/m) E^0 dt/2 (initial-state option).
+//
+// Gather tables (E, dt/h, neighbour ratios; for FP64 the nodes and widths)
+// are staged in LDS when a workgroup enters a segment.  The deposit goes to
+// an LDS int64 copy of the grid: each lane first merges its own run of equal
+// cells, then runs of equal cells across the wavefront are summed by their
+// first lane (sorted particles make nearly every lane of a wavefront share
+// one or two cells), and only the run leaders issue LDS atomics.  At the end
+// of a segment the nonzero LDS entries are added to HBM with one atomic each.
+#include "device.h"
+#include "kernels.h"
+
+namespace ecpic {
+
+constexpr double kHALF_ME_OVER_QE = (0.5 * kME) / kQE;
+constexpr double kTWO_QE_OVER_ME = (2.0 * kQE) / kME;
+constexpr double kTWO_ME_OVER_M = (2.0 * kME) / kMAR;
+constexpr int kPPT = 4;                     // particles per thread per tile
+constexpr float kWalkLimit = 4194304.0f;    // |sigma| beyond 2^22 cells: out of any grid
+
+// ---------------------------------------------------------------------------
+// Locating positions (FP64 form) -- the deposit contract.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int locate64(const InstDev &I, const double *nodes, const double *h,
+                                        double x, double &xi) {
+  const int N = I.N;
+  int j;
+  double f;
+  if (I.uniform) {
+    const double s = x / I.dx;
+    const double jf = floor(s);
+    j = (int)jf;
+    if (j >= N) j = N - 1;
+    f = s - (double)j;
+  } else {
+    int lo = 0, hi = N;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (nodes[mid] <= x) lo = mid;
+      else hi = mid;
+    }
+    j = lo;
+    f = (x - nodes[j]) / h[j];
+  }
+  xi = fmin(fmax(f, 0.0), 1.0);
+  return j;
+}
+
+// FP32 state of an FP64 position: off = (float) xi, moved to the next cell when
+// it rounds up to 1 (kept below 1 in the last cell of a bounded grid).
+__device__ __forceinline__ void to_state32(const InstDev &I, double x, int &cell, float &off) {
+  double xi;
+  int j = locate64(I, I.nodes, I.h, x, xi);
+  float o = (float)xi;
+  if (o >= 1.0f) {
+    if (j + 1 < I.N) { j += 1; o = 0.0f; }
+    else if (I.bc == 1) { j = 0; o = 0.0f; }
+    else o = 0x1.fffffep-1f;
+  }
+  cell = j;
+  off = o;
+}
+
+__device__ __forceinline__ void weights(double xi, int64_t &w0, int64_t &w1) {
+  w1 = (int64_t)rint(xi * 4294967296.0);
+  w0 = (int64_t)4294967296LL - w1;
+}
+
+// ---------------------------------------------------------------------------
+// FP32 cell walk.  Returns 0 (inside), -1 / +1 (left the bounded grid on that
+// side) or 2 (non-finite or runaway).  Order of operations:
+//   while sigma < 0:  j -= 1 (wrap), sigma = 1 + sigma * (h_{j+1}/h_j)
+//   while sigma >= 1: sigma = (sigma - 1) * (h_j/h_{j+1}), j += 1 (wrap)
+// On a uniform grid both loops collapse to sigma - floor(sigma) (exact when
+// moving right, one rounding when moving left, identical to the loop) plus a
+// carry when the left move rounds up to 1.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int walk32(const InstDev &I, const float *rf, const float *rb, int &j,
+                                      float &sig) {
+  const int N = I.N;
+  const bool periodic = I.bc == 1;
+  if (!(fabsf(sig) < kWalkLimit)) {
+    if (sig != sig || periodic) return 2;
+    return sig < 0.0f ? -1 : 1;
+  }
+  if (I.uniform) {
+    if (sig < 0.0f || sig >= 1.0f) {
+      const float m = floorf(sig);
+      float r = sig - m;
+      int jj = j + (int)m;
+      if (r >= 1.0f) { r = 0.0f; jj += 1; }
+      if (periodic) {
+        jj %= N;
+        if (jj < 0) jj += N;
+      } else if (jj < 0) {
+        return -1;
+      } else if (jj >= N) {
+        return 1;
+      }
+      j = jj;
+      sig = r;
+    }
+    return 0;
+  }
+  int guard = 0;
+  while (sig < 0.0f) {
+    j -= 1;
+    if (j < 0) {
+      if (!periodic) return -1;
+      j += N;
+    }
+    const float tt = sig * rb[j];
+    sig = 1.0f + tt;
+    if (++guard > 4 * N + 64) return 2;
+  }
+  while (sig >= 1.0f) {
+    sig = (sig - 1.0f) * rf[j];
+    j += 1;
+    if (j >= N) {
+      if (!periodic) return 1;
+      j -= N;
+    }
+    if (++guard > 4 * N + 64) return 2;
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Collisions (argon, analytic cross sections), in FP64 for both state forms.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double sig_el(double e) { return 1.0e-19 / (1.0 + e / 20.0); }
+__device__ __forceinline__ double lnx_over_x(double e, double thr, double amp) {
+  if (!(e > thr)) return 0.0;
+  const double x = e / thr;
+  return amp * log(x) / x;
+}
+__device__ __forceinline__ void iso_dir(double ua, double ub, double &dx, double &dy, double &dz) {
+  const double ct = 1.0 - 2.0 * ua;
+  const double st = sqrt(fmax(0.0, 1.0 - ct * ct));
+  const double a = kTWO_PI * ub;
+  dx = ct;
+  dy = st * cos(a);
+  dz = st * sin(a);
+}
+__device__ __forceinline__ void gas_velocity(const InstDev &I, uint64_t id, int64_t k, int s,
+                                             double &gx, double &gy, double &gz) {
+  const uint4 g = philox((uint32_t)k, TAG_GAS | (uint32_t)(s << 8), I.seed, id);
+  double z0, z1, z2, z3;
+  box_muller(u32d(g.x), u32d(g.y), z0, z1);
+  box_muller(u32d(g.z), u32d(g.w), z2, z3);
+  gx = I.vti * z0;
+  gy = I.vti * z1;
+  gz = I.vti * z2;
+}
+
+// Electron null collision.  Returns the process (0 null, 1 elastic,
+// 2 excitation, 3 ionisation); ej receives the ejected electron's velocity.
+__device__ int collide_electron(const InstDev &I, uint64_t id, int64_t k, double &vx, double &vy,
+                                double &vz, bool &bound, double ej[3]) {
+  const uint4 r = philox((uint32_t)k, TAG_COLL, I.seed, id);
+  const double u1 = u32d(r.x), u2 = u32d(r.y), u3 = u32d(r.z);
+  const double v2 = (vx * vx + vy * vy) + vz * vz;
+  const double speed = sqrt(v2);
+  const double eps = kHALF_ME_OVER_QE * v2;
+  const double nu_el = (I.n_g * sig_el(eps)) * speed;
+  const double nu_ex = (I.n_g * lnx_over_x(eps, kEXC, 2.7e-20)) * speed;
+  const double nu_iz = (I.n_g * lnx_over_x(eps, kION, 7.6e-20)) * speed;
+  const double s_el_ex = nu_el + nu_ex;
+  const double s_all = s_el_ex + nu_iz;
+  const double R = u1 * I.nu_max[0];
+  bound = s_all > I.nu_max[0];
+  const int proc = (R < nu_el) ? 1 : ((R < s_el_ex) ? 2 : ((R < s_all) ? 3 : 0));
+  if (proc == 0) return 0;
+  double dx, dy, dz;
+  iso_dir(u2, u3, dx, dy, dz);
+  double s;
+  if (proc == 1) {
+    const double cos_chi = ((vx * dx + vy * dy) + vz * dz) / speed;
+    const double f = 1.0 - kTWO_ME_OVER_M * (1.0 - cos_chi);
+    s = speed * sqrt(f);
+  } else if (proc == 2) {
+    s = sqrt((eps - kEXC) * kTWO_QE_OVER_ME);
+  } else {
+    s = sqrt((0.5 * (eps - kION)) * kTWO_QE_OVER_ME);
+  }
+  vx = s * dx;
+  vy = s * dy;
+  vz = s * dz;
+  if (proc == 3) {
+    const uint4 q = philox((uint32_t)k, TAG_EJECT, I.seed, id);
+    double ex, ey, ez;
+    iso_dir(u32d(q.x), u32d(q.y), ex, ey, ez);
+    ej[0] = s * ex;
+    ej[1] = s * ey;
+    ej[2] = s * ez;
+  }
+  return proc;
+}
+
+// Ion charge exchange with a gas atom drawn from the gas Maxwellian.
+__device__ bool collide_ion(const InstDev &I, uint64_t id, int64_t k, double &vx, double &vy,
+                            double &vz, bool &bound) {
+  const uint4 r = philox((uint32_t)k, TAG_COLL | (1u << 8), I.seed, id);
+  const double u1 = u32d(r.x);
+  double gx, gy, gz;
+  gas_velocity(I, id, k, 1, gx, gy, gz);
+  const double ddx = vx - gx, ddy = vy - gy, ddz = vz - gz;
+  const double g = sqrt((ddx * ddx + ddy * ddy) + ddz * ddz);
+  const double nu = (I.n_g * kSIGMA_CX) * g;
+  bound = nu > I.nu_max[1];
+  const bool cx = (u1 * I.nu_max[1]) < nu;
+  if (cx) {
+    vx = gx;
+    vy = gy;
+    vz = gz;
+  }
+  return cx;
+}
+
+// ---------------------------------------------------------------------------
+// Shared state of a workgroup
+// ---------------------------------------------------------------------------
+struct Smem {
+  int seg_prefix[2 * kMaxInst + 1];
+  unsigned long long ctr[kNctr];
+  int is_last;
+};
+
+template <int BLOCK>
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Deposit of one record per lane (key = cell j, a0 -> node j, a1 -> node j+1)
+// into the LDS grid.  Runs of equal keys across the wavefront are summed and
+// added by their first lane; up to 4 rounds, then the rest go directly.
+__device__ __forceinline__ void deposit_wave(int64_t *sA, bool has, int key, unsigned long long a0,
+                                             unsigned long long a1) {
+  const int lane = __lane_id();
+  unsigned long long pending = __ballot(has);
+  int rounds = 0;
+  while (pending && rounds < 4) {
+    const int leader = __ffsll((long long)pending) - 1;
+    const int lkey = __shfl(key, leader, 64);
+    const bool match = has && key == lkey;
+    const unsigned long long mm = __ballot(match);
+    const unsigned long long s0 = wave_sum_u64<64>(match ? a0 : 0ull);
+    const unsigned long long s1 = wave_sum_u64<64>(match ? a1 : 0ull);
+    if (lane == leader) {
+      atomicAdd(reinterpret_cast<unsigned long long *>(&sA[lkey]), s0);
+      atomicAdd(reinterpret_cast<unsigned long long *>(&sA[lkey + 1]), s1);
+    }
+    if (match) has = false;
+    pending &= ~mm;
+    ++rounds;
+    if (__popcll(mm) < 4) break;   // scattered keys: stop merging
+  }
+  if (has) {
+    atomicAdd(reinterpret_cast<unsigned long long *>(&sA[key]), a0);
+    atomicAdd(reinterpret_cast<unsigned long long *>(&sA[key + 1]), a1);
+  }
+}
+
+// Per-thread accumulation of up to kPPT deposits: the run of the first valid
+// cell stays in registers for the wavefront merge, other cells go to LDS.
+struct DepAcc {
+  bool has;
+  int key;
+  unsigned long long a0, a1;
+  __device__ void init() { has = false; key = 0; a0 = 0; a1 = 0; }
+  __device__ void add(int64_t *sA, int j, int64_t w0, int64_t w1) {
+    if (!has) { has = true; key = j; a0 = (unsigned long long)w0; a1 = (unsigned long long)w1; }
+    else if (j == key) { a0 += (unsigned long long)w0; a1 += (unsigned long long)w1; }
+    else {
+      atomicAdd(reinterpret_cast<unsigned long long *>(&sA[j]), (unsigned long long)w0);
+      atomicAdd(reinterpret_cast<unsigned long long *>(&sA[j + 1]), (unsigned long long)w1);
+    }
+  }
+};
+
+__device__ __forceinline__ void global_deposit(int64_t *A, int j, int64_t w0, int64_t w1) {
+  atomicAdd(reinterpret_cast<unsigned long long *>(&A[j]), (unsigned long long)w0);
+  atomicAdd(reinterpret_cast<unsigned long long *>(&A[j + 1]), (unsigned long long)w1);
+}
+
+__device__ __forceinline__ void set_status(InstState &S, int bits) {
+  atomicOr(&S.status, bits);
+}
+
+__device__ __forceinline__ bool eedf_due(const InstDev &I, int64_t k) {
+  return I.eedf_every > 0 && k >= I.avg_start && ((k - I.avg_start) % I.eedf_every) == 0;
+}
+
+__device__ __forceinline__ void eedf_sample(const InstDev &I, double x, double vx, double vy,
+                                            double vz) {
+  if (!(fabs(x - I.eedf_centre) < I.eedf_half)) return;
+  const double eps = kHALF_ME_OVER_QE * ((vx * vx + vy * vy) + vz * vz);
+  const double b = floor(eps / I.eedf_de);
+  if (b < (double)I.eedf_bins) atomicAdd(&I.eedf[(int)b], 1ull);
+}
+
+// Reserve a slot for a new particle of species s; -1 when the segment is full.
+__device__ __forceinline__ int64_t append_slot(const InstDev &I, InstState &S, int s) {
+  const unsigned long long a = atomicAdd(&S.append[s], 1ull);
+  const int64_t idx = S.extent[s] + (int64_t)a;
+  if (idx >= I.cap[s]) {
+    set_status(S, ST_CAPACITY);
+    return -1;
+  }
+  return idx;
+}
+
+// ---------------------------------------------------------------------------
+// Form traits
+// ---------------------------------------------------------------------------
+struct F32 {
+  static constexpr int prec = 1;
+  using V = float;
+  using View = P32;
+  static __device__ View view(const InstDev &I, int s, int buf) { return view32(I.pbuf[s][buf], I.cap[s]); }
+};
+struct F64 {
+  static constexpr int prec = 0;
+  using V = double;
+  using View = P64;
+  static __device__ View view(const InstDev &I, int s, int buf) { return view64(I.pbuf[s][buf], I.cap[s]); }
+};
+
+// Write a new particle (SEE electron or ionisation product).
+template <class F>
+__device__ void write_new(const InstDev &I, typename F::View P, int64_t idx, double x, int cell,
+                         float off, double vx, double vy, double vz, uint64_t id, int32_t kn) {
+  if constexpr (F::prec == 1) {
+    P.cell[idx] = cell;
+    P.off[idx] = off;
+    P.vx[idx] = (float)vx;
+    P.vy[idx] = (float)vy;
+    P.vz[idx] = (float)vz;
+  } else {
+    P.x[idx] = x;
+    P.vx[idx] = vx;
+    P.vy[idx] = vy;
+    P.vz[idx] = vz;
+  }
+  P.knext[idx] = kn;
+  P.id[idx] = id;
+}
+
+// Secondary emission by an ion absorbed at `wall` during step k.  The new
+// electron goes straight into the electron deposit of step k+1 when `dep`.
+template <class F>
+__device__ void emit_secondary(const InstDev &I, InstState &S, Smem &sm, uint64_t ion_id, int wall,
+                               int64_t k, int buf, bool dep, int64_t *A_next_e) {
+  const uint4 r = philox((uint32_t)k, TAG_SEE | (1u << 8), I.seed, ion_id);
+  if (!(u32d(r.x) < I.gamma_see)) return;
+  const uint4 p = philox((uint32_t)k, TAG_SEE_POS | (1u << 8), I.seed, ion_id);
+  const double vxm = I.vt_see * sqrt(-2.0 * log(u32d(r.y)));
+  double zy, zz;
+  box_muller(u32d(r.z), u32d(r.w), zy, zz);
+  const double d = (vxm * I.dt) * u32d(p.x);
+  const bool left = wall < 0;
+  const double x = left ? d : I.L - d;
+  const double vx = left ? vxm : -vxm;
+  if (!(x >= 0.0 && x < I.L)) return;
+  const uint64_t cid = (uint64_t)p.y | ((uint64_t)p.z << 32);
+  const int32_t kn = next_candidate(cid, k, 0, I.seed, I.nudt[0]);
+  int cell = 0;
+  float off = 0.0f;
+  double xi;
+  int j;
+  if constexpr (F::prec == 1) {
+    to_state32(I, x, cell, off);
+    j = cell;
+    xi = (double)off;
+  } else {
+    j = locate64(I, I.nodes, I.h, x, xi);
+  }
+  const int64_t idx = append_slot(I, S, 0);
+  if (idx < 0) return;
+  write_new<F>(I, F::view(I, 0, buf), idx, x, cell, off, vx, I.vt_see * zy, I.vt_see * zz, cid, kn);
+  atomicAdd(&sm.ctr[C_SEE], 1ull);
+  if (dep) {
+    int64_t w0, w1;
+    weights(xi, w0, w1);
+    global_deposit(A_next_e, j, w0, w1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The persistent particle kernel
+// ---------------------------------------------------------------------------
+template <class F, int MODE, int BLOCK>
+__global__ void __launch_bounds__(BLOCK)
+k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, int n_inst, int max_n,
+            unsigned int *__restrict__ done) {
+  constexpr int TILE = BLOCK * kPPT;
+  __shared__ Smem sm;
+  extern __shared__ __align__(16) unsigned char dsm[];
+  const int t = threadIdx.x;
+  const int np1 = max_n + 1;
+  int64_t *sA = reinterpret_cast<int64_t *>(dsm);
+  // FP32: E f32[np1], dt/h f32[max_n], forward and backward ratios f32[max_n].
+  float *sE32 = reinterpret_cast<float *>(sA + np1);
+  float *sDtoh = sE32 + np1;
+  float *sRf = sDtoh + max_n;
+  float *sRb = sRf + max_n;
+  // FP64: E f64[np1], nodes f64[np1], widths f64[max_n].
+  double *sE64 = reinterpret_cast<double *>(sA + np1);
+  double *sNodes = sE64 + np1;
+  double *sH = sNodes + np1;
+
+  // Tile prefix over the segments (inst, species) that advance this pass.
+  const int nseg = 2 * n_inst;
+  for (int s = t; s < nseg; s += BLOCK) {
+    const InstDev &I = insts[s >> 1];
+    const InstState &S = states[s >> 1];
+    const int sp = s & 1;
+    const bool ok = I.active && S.frozen == 0 && sp < I.nsp && !(I.k_stop > 0 && S.k >= I.k_stop);
+    const int64_t ext = ok ? S.extent[sp] : 0;
+    sm.seg_prefix[s + 1] = (int)((ext + TILE - 1) / TILE);
+  }
+  if (t == 0) sm.seg_prefix[0] = 0;
+  if (t < kNctr) sm.ctr[t] = 0;
+  if (MODE == M_DEPOSIT || MODE == M_FUSED)
+    for (int j = t; j < np1; j += BLOCK) sA[j] = 0;
+  __syncthreads();
+  if (t == 0) {
+    for (int s = 1; s <= nseg; ++s) sm.seg_prefix[s] += sm.seg_prefix[s - 1];
+  }
+  __syncthreads();
+  const int64_t T = sm.seg_prefix[nseg];
+  const int64_t t0 = T * blockIdx.x / gridDim.x;
+  const int64_t t1 = T * (blockIdx.x + 1) / gridDim.x;
+
+  int seg = -1;
+  const InstDev *Ip = nullptr;
+  InstState *Sp = nullptr;
+  int sp = 0, buf = 0, N = 0;
+  int64_t k = 0, ext = 0, seg_first = 0;
+  typename F::View P;
+  int64_t *A_out = nullptr;     // deposit target (HBM) of this segment
+  int64_t *A_next_other = nullptr;
+  bool deposit_on = false;
+  unsigned long long live_here = 0;
+
+  auto flush = [&]() {
+    // Deposit: nonzero LDS entries -> HBM (periodic: node N folds into 0).
+    __syncthreads();
+    if (deposit_on) {
+      if (Ip->bc == 1 && t == 0) {
+        const int64_t v = sA[0] + sA[N];
+        sA[0] = v;
+        sA[N] = v;
+      }
+      __syncthreads();
+      for (int j = t; j <= N; j += BLOCK) {
+        const int64_t v = sA[j];
+        if (v != 0) {
+          atomicAdd(reinterpret_cast<unsigned long long *>(&A_out[j]), (unsigned long long)v);
+          sA[j] = 0;
+        }
+      }
+    }
+    // Live count of this segment (particle-steps) and the shared counters.
+    const unsigned long long lw = wave_sum_u64<64>(live_here);
+    if (__lane_id() == 0 && lw) atomicAdd(&sm.ctr[C_PSTEPS], lw);
+    live_here = 0;
+    __syncthreads();
+    if (t < kNctr) {
+      const unsigned long long v = sm.ctr[t];
+      if (v) {
+        if (t == C_PSTEPS && MODE != M_DEPOSIT && MODE != M_MCC && MODE != M_PULLBACK) {
+          atomicAdd(&Sp->ctr[C_PSTEPS], v);
+          atomicAdd(&Sp->step_live[sp], v);
+        } else if (t >= C_ABS && t < C_ABS + 4) {
+          atomicAdd(&Sp->ctr[t], v);
+          atomicAdd(&Sp->step_absorbed[(t - C_ABS) >> 1], v);
+        } else if (t != C_PSTEPS) {
+          atomicAdd(&Sp->ctr[t], v);
+        }
+        sm.ctr[t] = 0;
+      }
+    }
+    __syncthreads();
+  };
+
+  for (int64_t tile = t0; tile < t1; ++tile) {
+    // Segment of this tile (uniform across the workgroup).
+    int s = seg < 0 ? 0 : seg;
+    while (sm.seg_prefix[s + 1] <= tile) ++s;
+    s = __builtin_amdgcn_readfirstlane(s);
+    if (s != seg) {
+      if (seg >= 0) flush();
+      seg = s;
+      Ip = &insts[seg >> 1];
+      Sp = &states[seg >> 1];
+      sp = seg & 1;
+      const InstDev &I = *Ip;
+      N = I.N;
+      k = Sp->k;
+      buf = Sp->parity;
+      ext = Sp->extent[sp];
+      seg_first = sm.seg_prefix[seg];
+      P = F::view(I, sp, buf);
+      const int par = (int)(k & 1);
+      deposit_on = (MODE == M_DEPOSIT) || (MODE == M_FUSED);
+      A_out = (MODE == M_DEPOSIT) ? I.A[par][sp] : I.A[par ^ 1][sp];
+      A_next_other = I.A[par ^ 1][sp ^ 1];
+      // Stage the gather tables.
+      if constexpr (F::prec == 1) {
+        if (MODE != M_DEPOSIT && MODE != M_MCC) {
+          const int ne = (I.gather == 0) ? N : N + 1;
+          for (int j = t; j < ne; j += BLOCK) sE32[j] = I.E32[j];
+          if (!I.uniform) {
+            for (int j = t; j < N; j += BLOCK) {
+              sDtoh[j] = I.dtoh32[j];
+              sRf[j] = I.rf32[j];
+              sRb[j] = I.rb32[j];
+            }
+          }
+        }
+      } else {
+        if (MODE != M_MCC) {
+          const int ne = (I.gather == 0) ? N : N + 1;
+          if (MODE != M_DEPOSIT)
+            for (int j = t; j < ne; j += BLOCK) sE64[j] = I.E64[j];
+          if (!I.uniform) {
+            for (int j = t; j <= N; j += BLOCK) sNodes[j] = I.nodes[j];
+            for (int j = t; j < N; j += BLOCK) sH[j] = I.h[j];
+          }
+        }
+      }
+      __syncthreads();
+    }
+    const InstDev &I = *Ip;
+    InstState &S = *Sp;
+    const int64_t base = (tile - seg_first) * TILE;
+    const int64_t i0 = base + (int64_t)t * kPPT;
+    const bool full = i0 + kPPT <= ext;
+    const bool due_eedf = (MODE == M_PUSH || MODE == M_FUSED) && sp == 0 && eedf_due(I, k);
+    const double nudt = I.nudt[sp];
+    DepAcc dep;
+    dep.init();
+
+    if constexpr (F::prec == 1) {
+      // ---------------- FP32-state form ----------------
+      int c[kPPT];
+      float o[kPPT], vx[kPPT];
+      int kn[kPPT];
+      if (full) {
+        const int4 c4 = *reinterpret_cast<const int4 *>(P.cell + i0);
+        c[0] = c4.x; c[1] = c4.y; c[2] = c4.z; c[3] = c4.w;
+        {
+          const float4 o4 = *reinterpret_cast<const float4 *>(P.off + i0);
+          o[0] = o4.x; o[1] = o4.y; o[2] = o4.z; o[3] = o4.w;
+        }
+        if (MODE != M_DEPOSIT) {
+          const float4 v4 = *reinterpret_cast<const float4 *>(P.vx + i0);
+          vx[0] = v4.x; vx[1] = v4.y; vx[2] = v4.z; vx[3] = v4.w;
+        }
+        if (MODE == M_MCC || MODE == M_FUSED) {
+          const int4 k4 = *reinterpret_cast<const int4 *>(P.knext + i0);
+          kn[0] = k4.x; kn[1] = k4.y; kn[2] = k4.z; kn[3] = k4.w;
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < kPPT; ++q) {
+          const int64_t i = i0 + q;
+          const bool v = i < ext;
+          c[q] = v ? P.cell[i] : -1;
+          o[q] = v ? P.off[i] : 0.0f;
+          vx[q] = v ? P.vx[i] : 0.0f;
+          kn[q] = v ? P.knext[i] : 0;
+        }
+      }
+      int cn[kPPT];
+      float on[kPPT];
+      float vn[kPPT];
+#pragma unroll
+      for (int q = 0; q < kPPT; ++q) {
+        cn[q] = c[q];
+        on[q] = o[q];
+        vn[q] = vx[q];
+        if (c[q] < 0) continue;   // dead slot
+        const int64_t i = i0 + q;
+        if constexpr (MODE == M_DEPOSIT) {
+          int64_t w0, w1;
+          weights((double)o[q], w0, w1);
+          dep.add(sA, c[q], w0, w1);
+          continue;
+        }
+        if constexpr (MODE == M_PULLBACK) {
+          const float e = (I.gather == 0) ? sE32[c[q]]
+                                          : ((1.0f - o[q]) * sE32[c[q]]) + (o[q] * sE32[c[q] + 1]);
+          vn[q] = vx[q] - I.hq32[sp] * e;
+          continue;
+        }
+        bool alive = true;
+        if constexpr (MODE == M_PUSH || MODE == M_FUSED) {
+          live_here += 1;
+          const int j = c[q];
+          const float e = (I.gather == 0) ? sE32[j]
+                                          : ((1.0f - o[q]) * sE32[j]) + (o[q] * sE32[j + 1]);
+          const float v1 = vx[q] + I.qmdt32[sp] * e;
+          const float dtoh = I.uniform ? I.dtoh32u : sDtoh[j];
+          float sig = o[q] + v1 * dtoh;
+          int jj = j;
+          const int wall = walk32(I, sRf, sRb, jj, sig);
+          vn[q] = v1;
+          if (wall != 0 || v1 != v1) {
+            alive = false;
+            cn[q] = -1;
+            if (wall == 2 || v1 != v1) {
+              set_status(S, ST_NONFINITE);
+              atomicAdd(&sm.ctr[C_NONFINITE], 1ull);
+            } else {
+              const int wi = wall < 0 ? 0 : 1;
+              atomicAdd(&sm.ctr[C_ABS + 2 * sp + wi], 1ull);
+              const double vy = (double)P.vy[i], vz = (double)P.vz[i], vxd = (double)v1;
+              const double en = (0.5 * I.mass[sp] / kQE) * ((vxd * vxd + vy * vy) + vz * vz);
+              atomicAdd(&sm.ctr[C_EABS + 2 * sp + wi], (unsigned long long)rint(en * 65536.0));
+              if (sp == 1 && I.gamma_see > 0.0 && I.nsp > 1)
+                emit_secondary<F>(I, S, sm, P.id[i], wall, k, buf, MODE == M_FUSED,
+                                  I.A[(k + 1) & 1][0]);
+            }
+          } else {
+            cn[q] = jj;
+            on[q] = sig;
+            if (due_eedf) {
+              const double x = I.uniform ? ((double)jj * I.dx + (double)sig * I.dx)
+                                         : (I.nodes[jj] + (double)sig * I.h[jj]);
+              if (fabs(x - I.eedf_centre) < I.eedf_half)
+                eedf_sample(I, x, (double)v1, (double)P.vy[i], (double)P.vz[i]);
+            }
+          }
+        }
+        if constexpr (MODE == M_MCC || MODE == M_FUSED) {
+          if (alive && nudt > 0.0 && kn[q] <= k) {
+            const uint64_t id = P.id[i];
+            double ux = (double)vn[q], uy = (double)P.vy[i], uz = (double)P.vz[i];
+            bool bound = false;
+            atomicAdd(&sm.ctr[C_CAND + sp], 1ull);
+            if (sp == 0) {
+              double ej[3];
+              const int proc = collide_electron(I, id, k, ux, uy, uz, bound, ej);
+              if (proc) atomicAdd(&sm.ctr[proc == 1 ? C_EL : (proc == 2 ? C_EX : C_IZ)], 1ull);
+              if (proc == 3 && I.nsp > 1) {
+                const uint4 ch = philox((uint32_t)k, TAG_CHILD, I.seed, id);
+                const uint64_t eid = (uint64_t)ch.x | ((uint64_t)ch.y << 32);
+                const uint64_t iid = (uint64_t)ch.z | ((uint64_t)ch.w << 32);
+                double gx, gy, gz;
+                gas_velocity(I, id, k, 0, gx, gy, gz);
+                const int64_t ie = append_slot(I, S, 0);
+                const int64_t ii = append_slot(I, S, 1);
+                const int cc = cn[q];
+                const float oo = on[q];
+                if (ie >= 0)
+                  write_new<F>(I, P, ie, 0.0, cc, oo, ej[0], ej[1], ej[2], eid,
+                               next_candidate(eid, k, 0, I.seed, I.nudt[0]));
+                if (ii >= 0)
+                  write_new<F>(I, F::view(I, 1, buf), ii, 0.0, cc, oo, gx, gy, gz, iid,
+                               next_candidate(iid, k, 1, I.seed, I.nudt[1]));
+                if constexpr (MODE == M_FUSED) {
+                  int64_t w0, w1;
+                  weights((double)oo, w0, w1);
+                  if (ie >= 0) {
+                    atomicAdd(reinterpret_cast<unsigned long long *>(&sA[cc]), (unsigned long long)w0);
+                    atomicAdd(reinterpret_cast<unsigned long long *>(&sA[cc + 1]), (unsigned long long)w1);
+                  }
+                  if (ii >= 0) global_deposit(A_next_other, cc, w0, w1);
+                }
+              }
+            } else {
+              if (collide_ion(I, id, k, ux, uy, uz, bound)) atomicAdd(&sm.ctr[C_CX], 1ull);
+            }
+            if (bound) atomicAdd(&sm.ctr[C_BOUND], 1ull);
+            vn[q] = (float)ux;
+            P.vy[i] = (float)uy;
+            P.vz[i] = (float)uz;
+            P.knext[i] = next_candidate(id, k, sp, I.seed, nudt);
+          }
+        }
+        if constexpr (MODE == M_FUSED) {
+          if (alive) {
+            int64_t w0, w1;
+            weights((double)on[q], w0, w1);
+            dep.add(sA, cn[q], w0, w1);
+          }
+        }
+      }
+      // Write back the streamed fields.
+      if constexpr (MODE != M_DEPOSIT) {
+        if (full) {
+          if constexpr (MODE == M_PUSH || MODE == M_FUSED) {
+            *reinterpret_cast<int4 *>(P.cell + i0) = make_int4(cn[0], cn[1], cn[2], cn[3]);
+            *reinterpret_cast<float4 *>(P.off + i0) = make_float4(on[0], on[1], on[2], on[3]);
+          }
+          *reinterpret_cast<float4 *>(P.vx + i0) = make_float4(vn[0], vn[1], vn[2], vn[3]);
+        } else {
+#pragma unroll
+          for (int q = 0; q < kPPT; ++q) {
+            const int64_t i = i0 + q;
+            if (i < ext) {
+              if constexpr (MODE == M_PUSH || MODE == M_FUSED) {
+                P.cell[i] = cn[q];
+                P.off[i] = on[q];
+              }
+              P.vx[i] = vn[q];
+            }
+          }
+        }
+      }
+    } else {
+      // ---------------- FP64 form ----------------
+      double x[kPPT], vx[kPPT];
+      int kn[kPPT];
+      if (full) {
+        const double2 xa = *reinterpret_cast<const double2 *>(P.x + i0);
+        const double2 xb = *reinterpret_cast<const double2 *>(P.x + i0 + 2);
+        x[0] = xa.x; x[1] = xa.y; x[2] = xb.x; x[3] = xb.y;
+        if (MODE != M_DEPOSIT) {
+          const double2 va = *reinterpret_cast<const double2 *>(P.vx + i0);
+          const double2 vb = *reinterpret_cast<const double2 *>(P.vx + i0 + 2);
+          vx[0] = va.x; vx[1] = va.y; vx[2] = vb.x; vx[3] = vb.y;
+        }
+        if (MODE == M_MCC || MODE == M_FUSED) {
+          const int4 k4 = *reinterpret_cast<const int4 *>(P.knext + i0);
+          kn[0] = k4.x; kn[1] = k4.y; kn[2] = k4.z; kn[3] = k4.w;
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < kPPT; ++q) {
+          const int64_t i = i0 + q;
+          const bool v = i < ext;
+          x[q] = v ? P.x[i] : -1.0;
+          vx[q] = v ? P.vx[i] : 0.0;
+          kn[q] = v ? P.knext[i] : 0;
+        }
+      }
+      double xn[kPPT], vn[kPPT];
+      const double *nodes = sNodes;
+      const double *hh = sH;
+#pragma unroll
+      for (int q = 0; q < kPPT; ++q) {
+        xn[q] = x[q];
+        vn[q] = vx[q];
+        if (!(x[q] >= 0.0)) continue;   // dead slot
+        const int64_t i = i0 + q;
+        if constexpr (MODE == M_DEPOSIT) {
+          double xi;
+          const int j = locate64(I, nodes, hh, x[q], xi);
+          int64_t w0, w1;
+          weights(xi, w0, w1);
+          dep.add(sA, j, w0, w1);
+          continue;
+        }
+        if constexpr (MODE == M_PULLBACK) {
+          double xi;
+          const int j = locate64(I, nodes, hh, x[q], xi);
+          const double e = (I.gather == 0) ? sE64[j] : (1.0 - xi) * sE64[j] + xi * sE64[j + 1];
+          vn[q] = vx[q] - I.hq[sp] * e;
+          continue;
+        }
+        bool alive = true;
+        if constexpr (MODE == M_PUSH || MODE == M_FUSED) {
+          live_here += 1;
+          double xi;
+          const int j = locate64(I, nodes, hh, x[q], xi);
+          const double e = (I.gather == 0) ? sE64[j] : (1.0 - xi) * sE64[j] + xi * sE64[j + 1];
+          const double v1 = vx[q] + I.qmdt[sp] * e;
+          double x1 = x[q] + v1 * I.dt;
+          vn[q] = v1;
+          int wall = 0;
+          if (I.bc == 1) {
+            if (!(fabs(x1) < 4.0 * I.L)) wall = 2;
+            else {
+              while (x1 < 0.0) x1 = x1 + I.L;
+              while (x1 >= I.L) x1 = x1 - I.L;
+            }
+          } else if (!(x1 >= 0.0 && x1 < I.L)) {
+            wall = (x1 < 0.0) ? -1 : ((x1 >= I.L) ? 1 : 2);
+          }
+          if (wall != 0) {
+            alive = false;
+            xn[q] = -1.0;
+            if (wall == 2) {
+              set_status(S, ST_NONFINITE);
+              atomicAdd(&sm.ctr[C_NONFINITE], 1ull);
+            } else {
+              const int wi = wall < 0 ? 0 : 1;
+              atomicAdd(&sm.ctr[C_ABS + 2 * sp + wi], 1ull);
+              const double vy = P.vy[i], vz = P.vz[i];
+              const double en = (0.5 * I.mass[sp] / kQE) * ((v1 * v1 + vy * vy) + vz * vz);
+              atomicAdd(&sm.ctr[C_EABS + 2 * sp + wi], (unsigned long long)rint(en * 65536.0));
+              if (sp == 1 && I.gamma_see > 0.0 && I.nsp > 1)
+                emit_secondary<F>(I, S, sm, P.id[i], wall, k, buf, MODE == M_FUSED,
+                                  I.A[(k + 1) & 1][0]);
+            }
+          } else {
+            xn[q] = x1;
+            if (due_eedf && fabs(x1 - I.eedf_centre) < I.eedf_half)
+              eedf_sample(I, x1, v1, P.vy[i], P.vz[i]);
+          }
+        }
+        if constexpr (MODE == M_MCC || MODE == M_FUSED) {
+          if (alive && nudt > 0.0 && kn[q] <= k) {
+            const uint64_t id = P.id[i];
+            double ux = vn[q], uy = P.vy[i], uz = P.vz[i];
+            bool bound = false;
+            atomicAdd(&sm.ctr[C_CAND + sp], 1ull);
+            if (sp == 0) {
+              double ej[3];
+              const int proc = collide_electron(I, id, k, ux, uy, uz, bound, ej);
+              if (proc) atomicAdd(&sm.ctr[proc == 1 ? C_EL : (proc == 2 ? C_EX : C_IZ)], 1ull);
+              if (proc == 3 && I.nsp > 1) {
+                const uint4 ch = philox((uint32_t)k, TAG_CHILD, I.seed, id);
+                const uint64_t eid = (uint64_t)ch.x | ((uint64_t)ch.y << 32);
+                const uint64_t iid = (uint64_t)ch.z | ((uint64_t)ch.w << 32);
+                double gx, gy, gz;
+                gas_velocity(I, id, k, 0, gx, gy, gz);
+                const int64_t ie = append_slot(I, S, 0);
+                const int64_t ii = append_slot(I, S, 1);
+                const double xx = xn[q];
+                if (ie >= 0)
+                  write_new<F>(I, P, ie, xx, 0, 0.0f, ej[0], ej[1], ej[2], eid,
+                               next_candidate(eid, k, 0, I.seed, I.nudt[0]));
+                if (ii >= 0)
+                  write_new<F>(I, F::view(I, 1, buf), ii, xx, 0, 0.0f, gx, gy, gz, iid,
+                               next_candidate(iid, k, 1, I.seed, I.nudt[1]));
+                if constexpr (MODE == M_FUSED) {
+                  double xi;
+                  const int j = locate64(I, nodes, hh, xx, xi);
+                  int64_t w0, w1;
+                  weights(xi, w0, w1);
+                  if (ie >= 0) {
+                    atomicAdd(reinterpret_cast<unsigned long long *>(&sA[j]), (unsigned long long)w0);
+                    atomicAdd(reinterpret_cast<unsigned long long *>(&sA[j + 1]), (unsigned long long)w1);
+                  }
+                  if (ii >= 0) global_deposit(A_next_other, j, w0, w1);
+                }
+              }
+            } else {
+              if (collide_ion(I, id, k, ux, uy, uz, bound)) atomicAdd(&sm.ctr[C_CX], 1ull);
+            }
+            if (bound) atomicAdd(&sm.ctr[C_BOUND], 1ull);
+            vn[q] = ux;
+            P.vy[i] = uy;
+            P.vz[i] = uz;
+            P.knext[i] = next_candidate(id, k, sp, I.seed, nudt);
+          }
+        }
+        if constexpr (MODE == M_FUSED) {
+          if (alive) {
+            double xi;
+            const int j = locate64(I, nodes, hh, xn[q], xi);
+            int64_t w0, w1;
+            weights(xi, w0, w1);
+            dep.add(sA, j, w0, w1);
+          }
+        }
+      }
+      if constexpr (MODE != M_DEPOSIT) {
+        if (full) {
+          if constexpr (MODE == M_PUSH || MODE == M_FUSED) {
+            *reinterpret_cast<double2 *>(P.x + i0) = make_double2(xn[0], xn[1]);
+            *reinterpret_cast<double2 *>(P.x + i0 + 2) = make_double2(xn[2], xn[3]);
+          }
+          *reinterpret_cast<double2 *>(P.vx + i0) = make_double2(vn[0], vn[1]);
+          *reinterpret_cast<double2 *>(P.vx + i0 + 2) = make_double2(vn[2], vn[3]);
+        } else {
+#pragma unroll
+          for (int q = 0; q < kPPT; ++q) {
+            const int64_t i = i0 + q;
+            if (i < ext) {
+              if constexpr (MODE == M_PUSH || MODE == M_FUSED) P.x[i] = xn[q];
+              P.vx[i] = vn[q];
+            }
+          }
+        }
+      }
+    }
+    if constexpr (MODE == M_DEPOSIT || MODE == M_FUSED) {
+      deposit_wave(sA, dep.has, dep.key, dep.a0, dep.a1);
+    }
+  }
+  if (seg >= 0) flush();
+
+  // The last workgroup to finish closes the step: new particles join the
+  // extents, the live count is updated and checked, and k advances.
+  if constexpr (MODE == M_MCC || MODE == M_FUSED) {
+    __threadfence();
+    __syncthreads();
+    if (t == 0) sm.is_last = (atomicAdd(done, 1u) == gridDim.x - 1);
+    __syncthreads();
+    if (sm.is_last) {
+      __threadfence();
+      for (int i = t; i < n_inst; i += BLOCK) {
+        const InstDev &I = insts[i];
+        InstState &S = states[i];
+        if (!I.active || S.frozen != 0 || (I.k_stop > 0 && S.k >= I.k_stop)) continue;
+        for (int s = 0; s < I.nsp; ++s) {
+          const unsigned long long app = atomicAdd(&S.append[s], 0ull);
+          const unsigned long long lv = atomicAdd(&S.step_live[s], 0ull);
+          const unsigned long long ab = atomicAdd(&S.step_absorbed[s], 0ull);
+          int64_t add = (int64_t)app;
+          if (S.extent[s] + add > I.cap[s]) add = I.cap[s] - S.extent[s];
+          S.extent[s] += add;
+          const int64_t live = (MODE == M_FUSED) ? ((int64_t)lv - (int64_t)ab + add)
+                                                 : (S.n_live[s] - (int64_t)ab + add);
+          S.n_live[s] = live;
+          if ((double)live > I.growth_limit * (double)I.n_init[s] && I.n_init[s] > 0)
+            atomicOr(&S.status, (int)ST_GROWTH);
+          S.append[s] = 0;
+          S.step_live[s] = 0;
+          S.step_absorbed[s] = 0;
+        }
+        S.k += 1;
+        if (atomicOr(&S.status, 0) != 0) S.frozen = 1;
+      }
+      if (t == 0) *done = 0u;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Initial load (Section 2b): one thread per particle.
+// ---------------------------------------------------------------------------
+template <class F>
+__global__ void __launch_bounds__(256)
+k_init(const InstDev *__restrict__ insts, InstState *__restrict__ states, int inst, int s,
+       double t_ev) {
+  const InstDev &I = insts[inst];
+  const int64_t n = I.n_init[s];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t id = (uint64_t)i;
+  const uint32_t sb = (uint32_t)(s << 8);
+  const uint4 r = philox(0u, TAG_INIT0 | sb, I.seed, id);
+  const uint4 q = philox(0u, TAG_INIT1 | sb, I.seed, id);
+  double x = u52d(r.x, r.y) * I.L;
+  const double top = nextafter(I.L, 0.0);
+  x = fmin(x, top);
+  double z0, z1, z2, z3;
+  box_muller(u32d(r.z), u32d(r.w), z0, z1);
+  box_muller(u32d(q.x), u32d(q.y), z2, z3);
+  const double vt = sqrt(t_ev * kQE / I.mass[s]);
+  const double vx = vt * z0, vy = vt * z1, vz = vt * z2;
+  const int32_t kn = (I.nudt[s] > 0.0) ? geometric(0.0, u52d(q.z, q.w), I.nudt[s]) : kINT32_MAX;
+  const int buf = states[inst].parity;
+  typename F::View P = F::view(I, s, buf);
+  int cell = 0;
+  float off = 0.0f;
+  if constexpr (F::prec == 1) to_state32(I, x, cell, off);
+  write_new<F>(I, P, i, x, cell, off, vx, vy, vz, id, kn);
+}
+
+// ---------------------------------------------------------------------------
+// Diagnostics of one instance: live counts, kinetic energy (2^-20 eV fixed
+// point, order independent), max |vx| of the electrons.
+// ---------------------------------------------------------------------------
+template <class F>
+__global__ void __launch_bounds__(256)
+k_diag(const InstDev *__restrict__ insts, const InstState *__restrict__ states, int inst,
+       unsigned long long *__restrict__ out) {
+  const InstDev &I = insts[inst];
+  const InstState &S = states[inst];
+  for (int s = 0; s < I.nsp; ++s) {
+    typename F::View P = F::view(I, s, S.parity);
+    const int64_t ext = S.extent[s];
+    unsigned long long live = 0, ke = 0;
+    double vmax = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ext;
+         i += (int64_t)gridDim.x * blockDim.x) {
+      double vx, vy, vz;
+      if constexpr (F::prec == 1) {
+        if (P.cell[i] < 0) continue;
+        vx = P.vx[i]; vy = P.vy[i]; vz = P.vz[i];
+      } else {
+        if (!(P.x[i] >= 0.0)) continue;
+        vx = P.vx[i]; vy = P.vy[i]; vz = P.vz[i];
+      }
+      live += 1;
+      const double en = (0.5 * I.mass[s] / kQE) * ((vx * vx + vy * vy) + vz * vz);
+      ke += (unsigned long long)rint(en * 1048576.0);
+      vmax = fmax(vmax, fabs(vx));
+    }
+    live = wave_sum_u64<64>(live);
+    ke = wave_sum_u64<64>(ke);
+    for (int o = 32; o > 0; o >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, o, 64));
+    if (__lane_id() == 0) {
+      atomicAdd(&out[D_LIVE0 + s], live);
+      atomicAdd(&out[D_KE0 + s], ke);
+      if (s == 0) atomicMax(&out[D_VMAX], (unsigned long long)__double_as_longlong(vmax));
+    }
+  }
+}
+
+__global__ void k_zero_deposit(const InstDev *__restrict__ insts, const InstState *__restrict__ states) {
+  const InstDev &I = insts[blockIdx.x];
+  const InstState &S = states[blockIdx.x];
+  if (!I.active) return;
+  const int par = (int)(S.k & 1);
+  for (int n = threadIdx.x; n <= I.N; n += blockDim.x) {
+    I.A[par][0][n] = 0;
+    if (I.nsp > 1) I.A[par][1][n] = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+size_t particle_lds_bytes(int prec, int max_n) {
+  const size_t np1 = (size_t)max_n + 1;
+  if (prec == 1) return np1 * 8 + np1 * 4 + 3 * (size_t)max_n * 4;
+  return np1 * 8 + np1 * 8 + np1 * 8 + (size_t)max_n * 8;
+}
+
+template <class F, int MODE, int BLOCK>
+static hipError_t launch_pk(const InstDev *insts, InstState *states, int n_inst, int grid,
+                            int max_n, unsigned int *done, hipStream_t s) {
+  const size_t lds = particle_lds_bytes(F::prec, max_n);
+  hipLaunchKernelGGL((k_particles<F, MODE, BLOCK>), dim3(grid), dim3(BLOCK), lds, s, insts, states,
+                     n_inst, max_n, done);
+  return hipGetLastError();
+}
+
+template <class F>
+static hipError_t launch_form(const InstDev *insts, InstState *states, int n_inst, int mode,
+                              int block, int grid, int max_n, unsigned int *done, hipStream_t s) {
+  if (mode == M_FUSED && block == 512)
+    return launch_pk<F, M_FUSED, 512>(insts, states, n_inst, grid, max_n, done, s);
+  if (mode == M_FUSED && block == 128)
+    return launch_pk<F, M_FUSED, 128>(insts, states, n_inst, grid, max_n, done, s);
+  switch (mode) {
+    case M_DEPOSIT: return launch_pk<F, M_DEPOSIT, 256>(insts, states, n_inst, grid, max_n, done, s);
+    case M_PUSH: return launch_pk<F, M_PUSH, 256>(insts, states, n_inst, grid, max_n, done, s);
+    case M_MCC: return launch_pk<F, M_MCC, 256>(insts, states, n_inst, grid, max_n, done, s);
+    case M_FUSED: return launch_pk<F, M_FUSED, 256>(insts, states, n_inst, grid, max_n, done, s);
+    case M_PULLBACK: return launch_pk<F, M_PULLBACK, 256>(insts, states, n_inst, grid, max_n, done, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_particles(const InstDev *insts, InstState *states, int n_inst, int prec, int mode,
+                            int block, int grid, int max_n, unsigned int *done, hipStream_t s) {
+  if (prec == 1) return launch_form<F32>(insts, states, n_inst, mode, block, grid, max_n, done, s);
+  return launch_form<F64>(insts, states, n_inst, mode, block, grid, max_n, done, s);
+}
+
+void launch_init(const InstDev *insts, InstState *states, int inst, int species, int prec,
+                 double t_ev, int64_t n, hipStream_t s) {
+  const int blocks = (int)((n + 255) / 256);
+  if (blocks == 0) return;
+  if (prec == 1)
+    hipLaunchKernelGGL(k_init<F32>, dim3(blocks), dim3(256), 0, s, insts, states, inst, species, t_ev);
+  else
+    hipLaunchKernelGGL(k_init<F64>, dim3(blocks), dim3(256), 0, s, insts, states, inst, species, t_ev);
+}
+
+void launch_diag(const InstDev *insts, InstState *states, int inst, int prec,
+                 unsigned long long *out, hipStream_t s) {
+  if (prec == 1)
+    hipLaunchKernelGGL(k_diag<F32>, dim3(1024), dim3(256), 0, s, insts, states, inst, out);
+  else
+    hipLaunchKernelGGL(k_diag<F64>, dim3(1024), dim3(256), 0, s, insts, states, inst, out);
+}
+
+void launch_zero_deposit(const InstDev *insts, InstState *states, int n_inst, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_deposit, dim3(n_inst), dim3(256), 0, s, insts, states);
+}
+
+}  // namespace ecpic

