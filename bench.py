@@ -1,0 +1,186 @@
+"""Throughput benchmark of the EC-PIC step on one MI355X.
+
+Workload: the large argon discharge (0.3 m gap, 2048-cell refined grid with
+max/min cell ratio 8, 32 M electrons + 32 M Ar+, 400 V at 13.56 MHz, 20 mTorr,
+dt = T_RF/1000, FP32 particle state with FP64 Poisson and diagnostics, cell
+sort every 20 steps), synthetic Maxwellian load from seed 3.
+
+One "step" is one pass of the whole hot path: field solve, gather + push +
+absorption + secondary emission + collisions + deposit of x^{k+1} for every
+particle, and the periodic cell sort.  Throughput = sum over the timed steps
+of the live particles at step start / wall time, with the state resident in
+HBM.  Prints one JSON line.
+
+Beside it: the FP64-form GPU path on the same workload (fewer steps), the
+roofline of the dominant kernel (fused particle pass) from HIP-event
+durations over the timed region, and the plain FP64 CPU oracle timed on a
+bounded sample of the same workload on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+os.environ.setdefault("OMP_NUM_THREADS", "1")
+os.environ.setdefault("OPENBLAS_NUM_THREADS", "1")
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published peak
+B_ALG = {1: 32.0, 0: 48.0}     # algorithmic bytes per particle-step (FP32 state, FP64)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_particle_kernel_large_traffic.json")
+KERNEL_SOURCES = ["paper_2308_13092_amd/csrc/kernels_particles.hip",
+                  "paper_2308_13092_amd/csrc/device.h"]
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the kernel source has changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    return t
+
+
+def run_gpu(cfg, steps, warmup, autotune=False):
+    import torch
+    from paper_2308_13092_amd import Context
+    ctx = Context([cfg])
+    if autotune:
+        from paper_2308_13092_amd.autotune import autotune as tune
+        tune(ctx)
+    ctx.step(warmup)
+    torch.cuda.synchronize()
+    d0 = ctx.diagnostics()
+    ctx.kernel_times(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = ctx.kernel_times(False)
+    d1 = ctx.diagnostics()
+    ps = int(d1["particle_steps"] - d0["particle_steps"])
+    el = t1 - t0
+    out = dict(value=ps / el, ms_per_step=1e3 * el / steps, particle_steps=ps, kt=kt,
+               live=[int(v) for v in d1["n_live"]], status=int(d1["status"]),
+               tuning=ctx.tuning())
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(n_per_species=2_000_000, seconds=12.0, min_steps=3):
+    """The oracle as it stands, on one host core, stepped until ``seconds``
+    of CPU work have elapsed (at least ``min_steps`` steps)."""
+    from oracle.sim import Sim
+    from paper_2308_13092_amd import configs
+    cfg = configs.large(n_per_species=n_per_species)
+    sim = Sim(cfg)
+    t0 = time.perf_counter()
+    ps = 0
+    steps = 0
+    while steps < min_steps or time.perf_counter() - t0 < seconds:
+        ps += sim.sp[0].n + sim.sp[1].n
+        sim.step()
+        steps += 1
+    el = time.perf_counter() - t0
+    return dict(value=ps / el, unit="particle-steps/s", cores=1, kind="oracle",
+                sample=(f"NumPy FP64 oracle, single thread: the large workload's grid, drive and "
+                        f"density with {n_per_species} e- + {n_per_species} Ar+ (weights scaled), "
+                        f"{steps} steps after the initial load ({el:.1f} s)"))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--fp64-steps", type=int, default=500)
+    ap.add_argument("--particles", type=int, default=32_000_000, help="per species")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--autotune", action="store_true")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the discharge "
+              f"instances shard across GPUs without any exchange, see the design notes.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2308_13092_amd import configs
+    torch.cuda.set_device(0)
+
+    cfg32 = configs.large(n_per_species=a.particles, precision=1)
+    r32 = run_gpu(cfg32, a.steps, a.warmup, autotune=a.autotune)
+    print(f"[bench] fp32-state: {r32['value']:.4g} p-s/s, {r32['ms_per_step']:.3f} ms/step, "
+          f"live {r32['live']}", file=sys.stderr, flush=True)
+    kt = r32["kt"]
+    avg_ms = kt["particle_ms"] / max(kt["particle_launches"], 1)
+    per_launch = r32["particle_steps"] / max(kt["particle_launches"], 1)
+    achieved = B_ALG[1] * per_launch / (avg_ms * 1e-3) / 1e9
+    tr = measured_traffic()
+    traffic = None if tr is None else tr["bytes_per_launch"]
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                    kernel="k_particles<F32, M_FUSED>", avg_launch_ms=round(avg_ms, 4),
+                    particles_per_launch=round(per_launch, 1), bytes_per_particle_step=B_ALG[1],
+                    field_ms_per_launch=round(kt["field_ms"] / max(kt["field_launches"], 1), 4),
+                    drain_ms_per_launch=round(kt["drain_ms"] / max(kt["drain_launches"], 1), 4),
+                    sort_ms_per_launch=round(kt["sort_ms"] / max(kt["sort_launches"], 1), 4))
+
+    fp64 = None
+    if not a.no_fp64:
+        cfg64 = configs.large(n_per_species=a.particles, precision=0)
+        r64 = run_gpu(cfg64, a.fp64_steps, a.warmup)
+        fp64 = dict(value=r64["value"], ms_per_step=r64["ms_per_step"], steps=a.fp64_steps,
+                    fp32_speedup=r32["value"] / r64["value"])
+        print(f"[bench] fp64: {r64['value']:.4g} p-s/s", file=sys.stderr, flush=True)
+
+    cpu = None if a.no_cpu else cpu_baseline()
+    line = {
+        "metric": "particle-steps/sec at 1 MI355X, FP32-state vs FP64 plain; p50/p99 sweep latency",
+        "value": r32["value"],
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": r32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": (f"large argon RF-CCP: 0.3 m gap, 2048-cell refined grid (ratio 8), "
+                                f"{a.particles} e- + {a.particles} Ar+, 400 V 13.56 MHz, 20 mTorr, "
+                                f"dt=T_RF/1000, FP32 state, sort every 20"),
+                   "particles": 2 * a.particles, "cells": 2048, "state": "fp32",
+                   "tuning": r32["tuning"]},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "fp64_plain": fp64,
+        "status": r32["status"],
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

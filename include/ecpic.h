@@ -154,7 +154,7 @@ typedef struct pic_state_view {
 
 /* Launch tuning (chosen by the autotuner, or set by hand). */
 typedef struct pic_tuning {
-  int32_t block;          /* threads per block of the particle kernels: 128, 256, 512 */
+  int32_t block;          /* threads per block of the fused particle kernel: 256, 512, 1024 */
   int32_t blocks_per_cu;  /* persistent particle-kernel blocks per compute unit (1-16;
                              0 = as many as the CU's LDS holds at once, at most 8)     */
   int32_t sort_interval;  /* steps between cell sorts (0 = never)                     */
@@ -165,7 +165,8 @@ typedef struct pic_tuning {
  * launches recorded since timing was enabled. */
 typedef struct pic_kernel_time {
   double field_ms;      int64_t field_launches;     /* Poisson + field (one block per instance) */
-  double particle_ms;   int64_t particle_launches;  /* fused gather/push/MCC/deposit pass       */
+  double particle_ms;   int64_t particle_launches;  /* streaming pass: gather, push, deposit    */
+  double drain_ms;      int64_t drain_launches;     /* queued particles: collisions, absorption */
   double sort_ms;       int64_t sort_launches;      /* cell sort + compaction (3 kernels)        */
   int64_t particles;    /* live particles processed by the timed particle launches */
 } pic_kernel_time;

@@ -84,8 +84,8 @@ struct SlotHost {
 
 // Grid block layout (offsets relative to the slot block).
 struct GridLayout {
-  size_t nodes, h, V, dtoh, rf, rb, A[2][2], phi, E64, E32, accA[2], acc_phi, eedf, scount[2],
-      scursor[2], particles, total;
+  size_t nodes, h, V, dtoh, rf, rb, runs, A[2][2], phi, E64, E32, accA[2], acc_phi, eedf, scount[2],
+      scursor[2], queue[2], particles, total;
 };
 
 int eff_bins(const pic_config &c) { return c.eedf_bins > 0 ? c.eedf_bins : 200; }
@@ -106,6 +106,7 @@ GridLayout layout(const pic_config &c) {
   g.dtoh = take(4 * N);
   g.rf = take(4 * N);
   g.rb = take(4 * N);
+  g.runs = take(4 * N);
   for (int p = 0; p < 2; ++p)
     for (int s = 0; s < 2; ++s) g.A[p][s] = take(8 * n1);
   g.phi = take(8 * n1);
@@ -117,6 +118,7 @@ GridLayout layout(const pic_config &c) {
   g.eedf = take(8 * (size_t)eff_bins(c));
   for (int s = 0; s < 2; ++s) g.scount[s] = take(8 * n1);
   for (int s = 0; s < 2; ++s) g.scursor[s] = take(8 * n1);
+  for (int s = 0; s < 2; ++s) g.queue[s] = take((s == 0 || c.n_species != 1) ? 4 * (size_t)eff_cap(c) : 0);
   g.particles = o;
   const int nsp = c.n_species == 1 ? 1 : 2;
   o += (size_t)nsp * 2 * align_up((size_t)eff_cap(c) * bytes_per_particle(c.precision));
@@ -151,7 +153,7 @@ std::string validate(const pic_config &c) {
   if (!(c.dt_s > 0.0) || !std::isfinite(c.dt_s)) return "dt_s must be positive";
   if (c.n_per_species < 0) return "n_per_species must be >= 0";
   if (c.capacity != 0 && c.capacity < c.n_per_species) return "capacity below n_per_species";
-  if (eff_cap(c) > ((int64_t)1 << 31)) return "capacity above 2^31";
+  if (eff_cap(c) > ((int64_t)1 << 30)) return "capacity above 2^30";
   if (c.n_per_species > 0 && !(c.weight_m2 > 0.0) && !(c.n0_m3 > 0.0))
     return "need weight_m2 > 0 or n0_m3 > 0";
   if (!(c.te_ev >= 0.0) || !(c.ti_ev >= 0.0)) return "temperatures must be >= 0";
@@ -209,7 +211,7 @@ struct pic_ctx {
   unsigned int *d_done = nullptr;   // [0] particles, [1] sort
   unsigned long long *d_diag = nullptr;
   int max_n = 2;
-  pic_tuning tune{256, 0, 0, 1};
+  pic_tuning tune{512, 0, 0, 1};
   int64_t host_step = 0;
   bool deposit_current = false;
   std::string err;
@@ -262,12 +264,13 @@ static void recompute_max_n(pic_ctx *c) {
 static int particle_grid(const pic_ctx *c) {
   int per = c->tune.blocks_per_cu;
   if (per <= 0) {
-    const size_t lds = particle_lds_bytes(c->prec, c->max_n) + 8192;
+    const size_t lds = particle_lds_bytes(c->prec, c->max_n, c->tune.block) + 8192;
     per = (int)std::min<size_t>(8, std::max<size_t>(1, (160 * 1024) / lds));
   }
   return c->n_cu * per;
 }
 static int sort_grid(const pic_ctx *c) { return c->n_cu * 4; }
+static int drain_grid(const pic_ctx *c) { return c->n_cu; }
 
 // Fill InstDev for slot i from its config and block offset; write host arrays.
 static pic_status setup_slot(pic_ctx *c, int i, const pic_config &cfg) {
@@ -313,6 +316,15 @@ static pic_status setup_slot(pic_ctx *c, int i, const pic_config &cfg) {
     dtoh[j] = (float)(dt / h[j]);
     rf[j] = (float)(h[j] / hn);
     rb[j] = (float)(hn / h[j]);
+  }
+  // Runs of cells joined by unit ratios (both directions): the walk crosses
+  // them in one step.  Cell j's run is [first, last], packed first | last << 16.
+  std::vector<int> runs(N);
+  for (int j = 0; j < N;) {
+    int e = j;
+    while (e + 1 < N && rf[e] == 1.0f && rb[e] == 1.0f) ++e;
+    for (int i = j; i <= e; ++i) runs[i] = j | (e << 16);
+    j = e + 1;
   }
 
   InstDev I;
@@ -377,6 +389,7 @@ static pic_status setup_slot(pic_ctx *c, int i, const pic_config &cfg) {
   I.dtoh32 = (float *)(base + g.dtoh);
   I.rf32 = (float *)(base + g.rf);
   I.rb32 = (float *)(base + g.rb);
+  I.runs = (int *)(base + g.runs);
   for (int p = 0; p < 2; ++p)
     for (int s = 0; s < 2; ++s) I.A[p][s] = (int64_t *)(base + g.A[p][s]);
   I.phi = (double *)(base + g.phi);
@@ -389,6 +402,7 @@ static pic_status setup_slot(pic_ctx *c, int i, const pic_config &cfg) {
   for (int s = 0; s < 2; ++s) {
     I.scount[s] = (unsigned long long *)(base + g.scount[s]);
     I.scursor[s] = (unsigned long long *)(base + g.scursor[s]);
+    I.queue[s] = (int *)(base + g.queue[s]);
   }
   const size_t pb = align_up((size_t)cap * bytes_per_particle(cfg.precision));
   for (int s = 0; s < I.nsp; ++s)
@@ -396,13 +410,14 @@ static pic_status setup_slot(pic_ctx *c, int i, const pic_config &cfg) {
   c->host_inst[i] = I;
 
   hipStream_t st = c->stream;
-  HIP_TRY(c, hipMemsetAsync(base, 0, g.particles, st));
+  HIP_TRY(c, hipMemsetAsync(base, 0, g.queue[0], st));
   HIP_TRY(c, hipMemcpyAsync(I.nodes, nodes.data(), 8 * (N + 1), hipMemcpyHostToDevice, st));
   HIP_TRY(c, hipMemcpyAsync(I.h, h.data(), 8 * N, hipMemcpyHostToDevice, st));
   HIP_TRY(c, hipMemcpyAsync(I.V, V.data(), 8 * (N + 1), hipMemcpyHostToDevice, st));
   HIP_TRY(c, hipMemcpyAsync(I.dtoh32, dtoh.data(), 4 * N, hipMemcpyHostToDevice, st));
   HIP_TRY(c, hipMemcpyAsync(I.rf32, rf.data(), 4 * N, hipMemcpyHostToDevice, st));
   HIP_TRY(c, hipMemcpyAsync(I.rb32, rb.data(), 4 * N, hipMemcpyHostToDevice, st));
+  HIP_TRY(c, hipMemcpyAsync(I.runs, runs.data(), 4 * N, hipMemcpyHostToDevice, st));
   HIP_TRY(c, hipMemcpyAsync(c->d_inst + i, &c->host_inst[i], sizeof(InstDev), hipMemcpyHostToDevice, st));
   InstState S;
   std::memset(&S, 0, sizeof S);
@@ -482,6 +497,7 @@ static pic_status flush_events(pic_ctx *c) {
     switch (c->ev_kind[p]) {
       case 0: c->times.field_ms += ms; c->times.field_launches++; break;
       case 1: c->times.particle_ms += ms; c->times.particle_launches++; break;
+      case 3: c->times.drain_ms += ms; c->times.drain_launches++; break;
       default: c->times.sort_ms += ms; c->times.sort_launches++; break;
     }
   }
@@ -511,6 +527,9 @@ static pic_status enqueue_step(pic_ctx *c, hipStream_t st, bool sort, bool timed
   if (timed) { pic_status r = ev_end(c); if (r) return r; r = ev_begin(c, 1); if (r) return r; }
   HIP_TRY(c, launch_particles(c->d_inst, c->d_state, c->n_inst, c->prec, M_FUSED, c->tune.block,
                               particle_grid(c), c->max_n, c->d_done, st));
+  if (timed) { pic_status r = ev_end(c); if (r) return r; r = ev_begin(c, 3); if (r) return r; }
+  HIP_TRY(c, launch_drain(c->d_inst, c->d_state, c->n_inst, c->prec, M_FUSED, drain_grid(c),
+                          c->d_done, st));
   if (timed) { pic_status r = ev_end(c); if (r) return r; }
   if (sort) {
     if (timed) { pic_status r = ev_begin(c, 2); if (r) return r; }
@@ -688,6 +707,8 @@ pic_status pic_gather_push(pic_ctx *c) {
   if (!c) return PIC_EINVAL;
   HIP_TRY(c, launch_particles(c->d_inst, c->d_state, c->n_inst, c->prec, M_PUSH, 256,
                               particle_grid(c), c->max_n, c->d_done, c->stream));
+  HIP_TRY(c, launch_drain(c->d_inst, c->d_state, c->n_inst, c->prec, M_PUSH, drain_grid(c),
+                          c->d_done, c->stream));
   c->deposit_current = false;
   return PIC_OK;
 }
@@ -696,6 +717,8 @@ pic_status pic_mcc(pic_ctx *c) {
   if (!c) return PIC_EINVAL;
   HIP_TRY(c, launch_particles(c->d_inst, c->d_state, c->n_inst, c->prec, M_MCC, 256,
                               particle_grid(c), c->max_n, c->d_done, c->stream));
+  HIP_TRY(c, launch_drain(c->d_inst, c->d_state, c->n_inst, c->prec, M_MCC, drain_grid(c),
+                          c->d_done, c->stream));
   c->deposit_current = false;
   c->host_step++;
   return PIC_OK;
@@ -1029,8 +1052,8 @@ size_t pic_pool_free(const pic_ctx *c) { return c ? c->pool.largest() : 0; }
 
 pic_status pic_set_tuning(pic_ctx *c, const pic_tuning *t) {
   if (!c || !t) return PIC_EINVAL;
-  if (t->block != 128 && t->block != 256 && t->block != 512)
-    return fail(c, PIC_EINVAL, "block must be 128, 256 or 512");
+  if (t->block != 256 && t->block != 512 && t->block != 1024)
+    return fail(c, PIC_EINVAL, "block must be 256, 512 or 1024");
   if (t->blocks_per_cu < 0 || t->blocks_per_cu > 16)
     return fail(c, PIC_EINVAL, "blocks_per_cu in [0, 16] (0 = as many as fit)");
   if (t->sort_interval < 0) return fail(c, PIC_EINVAL, "sort_interval must be >= 0");

@@ -71,12 +71,14 @@ struct InstDev {
   // grid block
   double *nodes, *h, *V;
   float *dtoh32, *rf32, *rb32;
+  int *runs;                   // per cell: first | last << 16 of its run of equal widths
   int64_t *A[2][2];            // [k parity][species]
   double *phi, *E64;
   float *E32;
   double *accA[2], *acc_phi;
   unsigned long long *eedf;
   unsigned long long *scount[2], *scursor[2];
+  int *queue[2];               // per-species queue of particles for the drain kernel
   // particles
   char *pbuf[2][2];            // [species][buffer]
 };
@@ -94,6 +96,7 @@ struct InstState {
   double field_energy, ne_max;
   int32_t n_samples, eedf_samples;
   int64_t sort_live[2];
+  unsigned long long qcount[2];   // queued particles of the current pass
 };
 
 // ---------------------------------------------------------------------------

@@ -9,7 +9,7 @@ namespace ecpic {
 enum Mode : int { M_DEPOSIT = 0, M_PUSH = 1, M_MCC = 2, M_FUSED = 3, M_PULLBACK = 4 };
 
 // Dynamic LDS bytes of the particle kernels for grids of up to max_n cells.
-size_t particle_lds_bytes(int prec, int max_n);
+size_t particle_lds_bytes(int prec, int max_n, int block);
 size_t sort_lds_bytes(int max_n);
 
 void launch_field(const InstDev *insts, InstState *states, int n_inst, int mode, hipStream_t s);
@@ -19,6 +19,10 @@ void launch_init(const InstDev *insts, InstState *states, int inst, int species,
 hipError_t launch_particles(const InstDev *insts, InstState *states, int n_inst, int prec,
                             int mode, int block, int grid, int max_n, unsigned int *done,
                             hipStream_t s);
+// Drain of the queued particles of a push / collision pass (closes the step
+// in the collision and fused modes).
+hipError_t launch_drain(const InstDev *insts, InstState *states, int n_inst, int prec, int mode,
+                        int grid, unsigned int *done, hipStream_t s);
 hipError_t launch_sort(const InstDev *insts, InstState *states, int n_inst, int prec, int grid,
                        int max_n, unsigned int *done, hipStream_t s);
 void launch_diag(const InstDev *insts, InstState *states, int inst, int prec,

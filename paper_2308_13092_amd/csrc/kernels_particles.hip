@@ -39,8 +39,7 @@ constexpr float kWalkLimit = 4194304.0f;    // |sigma| beyond 2^22 cells: out of
 // ---------------------------------------------------------------------------
 // Locating positions (FP64 form) -- the deposit contract.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int locate64(const InstDev &I, const double *nodes, const double *h,
-                                        double x, double &xi) {
+__device__ __forceinline__ int locate64(const InstDev &I, const double *nodes, double x, double &xi) {
   const int N = I.N;
   int j;
   double f;
@@ -58,7 +57,7 @@ __device__ __forceinline__ int locate64(const InstDev &I, const double *nodes, c
       else hi = mid;
     }
     j = lo;
-    f = (x - nodes[j]) / h[j];
+    f = (x - nodes[j]) / (nodes[j + 1] - nodes[j]);
   }
   xi = fmin(fmax(f, 0.0), 1.0);
   return j;
@@ -68,7 +67,7 @@ __device__ __forceinline__ int locate64(const InstDev &I, const double *nodes, c
 // it rounds up to 1 (kept below 1 in the last cell of a bounded grid).
 __device__ __forceinline__ void to_state32(const InstDev &I, double x, int &cell, float &off) {
   double xi;
-  int j = locate64(I, I.nodes, I.h, x, xi);
+  int j = locate64(I, I.nodes, x, xi);
   float o = (float)xi;
   if (o >= 1.0f) {
     if (j + 1 < I.N) { j += 1; o = 0.0f; }
@@ -83,18 +82,28 @@ __device__ __forceinline__ void weights(double xi, int64_t &w0, int64_t &w1) {
   w1 = (int64_t)rint(xi * 4294967296.0);
   w0 = (int64_t)4294967296LL - w1;
 }
+// The same weights for an FP32 offset: off * 2^32 is exact in FP32 and below
+// 2^32, so rounding it half-to-even in FP32 equals rint((double)off * 2^32).
+__device__ __forceinline__ void weights32(float off, int64_t &w0, int64_t &w1) {
+  const uint32_t r = (uint32_t)rintf(off * 4294967296.0f);
+  w1 = (int64_t)r;
+  w0 = (int64_t)4294967296LL - (int64_t)r;
+}
 
 // ---------------------------------------------------------------------------
 // FP32 cell walk.  Returns 0 (inside), -1 / +1 (left the bounded grid on that
-// side) or 2 (non-finite or runaway).  Order of operations:
+// side) or 2 (non-finite or runaway).  The contract is the cell-by-cell walk
 //   while sigma < 0:  j -= 1 (wrap), sigma = 1 + sigma * (h_{j+1}/h_j)
 //   while sigma >= 1: sigma = (sigma - 1) * (h_j/h_{j+1}), j += 1 (wrap)
-// On a uniform grid both loops collapse to sigma - floor(sigma) (exact when
-// moving right, one rounding when moving left, identical to the loop) plus a
-// carry when the left move rounds up to 1.
+// in FP32.  Inside a run of equal cells every step is sigma -= 1 (exact) or
+// sigma += 1 (exact while sigma <= -1), so m steps collapse into one
+// operation with the same result: sigma - m moving right, and fl(sigma + m)
+// moving left (only the last step rounds).  `run` packs, per cell, the first
+// (low 16 bits) and last (high 16 bits) cell of its run of equal widths; a
+// uniform grid is one run.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int walk32(const InstDev &I, const float *rf, const float *rb, int &j,
-                                      float &sig) {
+__device__ __forceinline__ int walk32(const InstDev &I, const float *rf, const float *rb,
+                                      const int *run, int &j, float &sig) {
   const int N = I.N;
   const bool periodic = I.bc == 1;
   if (!(fabsf(sig) < kWalkLimit)) {
@@ -121,23 +130,57 @@ __device__ __forceinline__ int walk32(const InstDev &I, const float *rf, const f
     return 0;
   }
   int guard = 0;
-  while (sig < 0.0f) {
-    j -= 1;
-    if (j < 0) {
-      if (!periodic) return -1;
-      j += N;
+  if (periodic) {
+    while (sig < 0.0f) {
+      j -= 1;
+      if (j < 0) j += N;
+      const float tt = sig * rb[j];
+      sig = 1.0f + tt;
+      if (++guard > 4 * N + 64) return 2;
     }
+    while (sig >= 1.0f) {
+      sig = (sig - 1.0f) * rf[j];
+      j += 1;
+      if (j >= N) j -= N;
+      if (++guard > 4 * N + 64) return 2;
+    }
+    return 0;
+  }
+  while (sig < 0.0f) {
+    const int lo = run[j] & 0xFFFF;
+    if (lo < j) {
+      const float m = -floorf(sig);
+      const int avail = j - lo;
+      if (m <= (float)avail) {
+        j -= (int)m;
+        sig = sig + m;
+        continue;
+      }
+      sig = sig + (float)avail;
+      j = lo;
+    }
+    j -= 1;
+    if (j < 0) return -1;
     const float tt = sig * rb[j];
     sig = 1.0f + tt;
     if (++guard > 4 * N + 64) return 2;
   }
   while (sig >= 1.0f) {
+    const int hi = run[j] >> 16;
+    if (hi > j) {
+      const float m = floorf(sig);
+      const int avail = hi - j;
+      if (m <= (float)avail) {
+        j += (int)m;
+        sig = sig - m;
+        continue;
+      }
+      sig = sig - (float)avail;
+      j = hi;
+    }
     sig = (sig - 1.0f) * rf[j];
     j += 1;
-    if (j >= N) {
-      if (!periodic) return 1;
-      j -= N;
-    }
+    if (j >= N) return 1;
     if (++guard > 4 * N + 64) return 2;
   }
   return 0;
@@ -393,7 +436,7 @@ __device__ void emit_secondary(const InstDev &I, InstState &S, Smem &sm, uint64_
     j = cell;
     xi = (double)off;
   } else {
-    j = locate64(I, I.nodes, I.h, x, xi);
+    j = locate64(I, I.nodes, x, xi);
   }
   const int64_t idx = append_slot(I, S, 0);
   if (idx < 0) return;
@@ -407,64 +450,134 @@ __device__ void emit_secondary(const InstDev &I, InstState &S, Smem &sm, uint64_
 }
 
 // ---------------------------------------------------------------------------
-// The persistent particle kernel
+// The particle pass: a streaming kernel and a drain kernel.
+//
+// k_particles (persistent) reads the state with vector loads, pushes every
+// live particle, deposits x^{k+1} into the LDS grid and writes the state back.
+// Particles that leave the gap or are collision candidates this step (a few
+// percent) are not handled in place: their indices go to a per-wavefront
+// queue in LDS (slots from a ballot) and, 64 at a time, to a per-segment queue
+// in HBM (one atomic per 64 entries).  k_drain then processes those queues
+// with full wavefronts: absorption tallies, secondary emission, the FP64
+// collision arithmetic and ionisation products.  Keeping the rare, heavy code
+// out of the streaming kernel keeps its register footprint small.
 // ---------------------------------------------------------------------------
-template <class F, int MODE, int BLOCK>
-__global__ void __launch_bounds__(BLOCK)
-k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, int n_inst, int max_n,
-            unsigned int *__restrict__ done) {
-  constexpr int TILE = BLOCK * kPPT;
-  __shared__ Smem sm;
-  extern __shared__ __align__(16) unsigned char dsm[];
-  const int t = threadIdx.x;
-  const int np1 = max_n + 1;
-  int64_t *sA = reinterpret_cast<int64_t *>(dsm);
-  // FP32: E f32[np1], dt/h f32[max_n], forward and backward ratios f32[max_n].
-  float *sE32 = reinterpret_cast<float *>(sA + np1);
-  float *sDtoh = sE32 + np1;
-  float *sRf = sDtoh + max_n;
-  float *sRb = sRf + max_n;
-  // FP64: E f64[np1], nodes f64[np1], widths f64[max_n].
-  double *sE64 = reinterpret_cast<double *>(sA + np1);
-  double *sNodes = sE64 + np1;
-  double *sH = sNodes + np1;
+// Queue entry: particle index | kind << 30; kind 0 = collision candidate,
+// 1 / 2 = absorbed at the left / right electrode, 3 = non-finite state.
+constexpr int kWaveQ = 320;   // per-wavefront LDS queue: 63 carried + 256 new entries fit
+constexpr int kQShift = 30;
+constexpr int kQMask = (1 << kQShift) - 1;
+__device__ __forceinline__ int qentry(int i, int kind) { return i | (kind << kQShift); }
 
-  // Tile prefix over the segments (inst, species) that advance this pass.
+// Tile prefix of the segments (inst, species) that advance in this pass.
+// `count_of` selects the per-segment work (particle extent or queue length).
+template <int BLOCK, class CountOf>
+__device__ int64_t segment_prefix(const InstDev *insts, const InstState *states, int n_inst,
+                                  int tile, int *prefix, CountOf count_of) {
   const int nseg = 2 * n_inst;
+  const int t = threadIdx.x;
   for (int s = t; s < nseg; s += BLOCK) {
     const InstDev &I = insts[s >> 1];
     const InstState &S = states[s >> 1];
     const int sp = s & 1;
     const bool ok = I.active && S.frozen == 0 && sp < I.nsp && !(I.k_stop > 0 && S.k >= I.k_stop);
-    const int64_t ext = ok ? S.extent[sp] : 0;
-    sm.seg_prefix[s + 1] = (int)((ext + TILE - 1) / TILE);
+    const int64_t n = ok ? count_of(S, sp) : 0;
+    prefix[s + 1] = (int)((n + tile - 1) / tile);
   }
-  if (t == 0) sm.seg_prefix[0] = 0;
+  if (t == 0) prefix[0] = 0;
+  __syncthreads();
+  if (t == 0)
+    for (int s = 1; s <= nseg; ++s) prefix[s] += prefix[s - 1];
+  __syncthreads();
+  return prefix[nseg];
+}
+
+// Flush the per-workgroup counters of one segment to its instance state.
+template <int BLOCK>
+__device__ void flush_counters(Smem &sm, InstState *Sp, int sp) {
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < kNctr) {
+    const unsigned long long v = sm.ctr[t];
+    if (v) {
+      if (t == C_PSTEPS) {
+        atomicAdd(&Sp->ctr[C_PSTEPS], v);
+        atomicAdd(&Sp->step_live[sp], v);
+      } else if (t >= C_ABS && t < C_ABS + 4) {
+        atomicAdd(&Sp->ctr[t], v);
+        atomicAdd(&Sp->step_absorbed[(t - C_ABS) >> 1], v);
+      } else {
+        atomicAdd(&Sp->ctr[t], v);
+      }
+      sm.ctr[t] = 0;
+    }
+  }
+  __syncthreads();
+}
+
+template <class F, int MODE, int BLOCK>
+__global__ void __launch_bounds__(BLOCK)
+k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, int n_inst, int max_n) {
+  constexpr int TILE = BLOCK * kPPT;
+  __shared__ Smem sm;
+  extern __shared__ __align__(16) unsigned char dsm[];
+  const int t = threadIdx.x;
+  const int lane = __lane_id();
+  const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int np1 = max_n + 1;
+  int64_t *sA = reinterpret_cast<int64_t *>(dsm);
+  // FP32: E f32[np1], dt/h f32[max_n], forward and backward ratios f32[max_n],
+  // runs of equal cells i32[max_n].
+  float *sE32 = reinterpret_cast<float *>(sA + np1);
+  float *sDtoh = sE32 + np1;
+  float *sRf = sDtoh + max_n;
+  float *sRb = sRf + max_n;
+  int *sRun = reinterpret_cast<int *>(sRb + max_n);
+  // FP64: E f64[np1], nodes f64[np1].
+  double *sE64 = reinterpret_cast<double *>(sA + np1);
+  double *sNodes = sE64 + np1;
+  const size_t tables = (F::prec == 1) ? (size_t)np1 * 12 + (size_t)max_n * 16 : (size_t)np1 * 24;
+  int *wq = reinterpret_cast<int *>(dsm + ((tables + 15) & ~(size_t)15)) + (t >> 6) * kWaveQ;
+  int wq_n = 0;   // entries in this wavefront's queue (wavefront-uniform)
+
   if (t < kNctr) sm.ctr[t] = 0;
   if (MODE == M_DEPOSIT || MODE == M_FUSED)
     for (int j = t; j < np1; j += BLOCK) sA[j] = 0;
-  __syncthreads();
-  if (t == 0) {
-    for (int s = 1; s <= nseg; ++s) sm.seg_prefix[s] += sm.seg_prefix[s - 1];
-  }
-  __syncthreads();
-  const int64_t T = sm.seg_prefix[nseg];
+  const int64_t T = segment_prefix<BLOCK>(insts, states, n_inst, TILE, sm.seg_prefix,
+                                          [](const InstState &S, int sp) { return S.extent[sp]; });
   const int64_t t0 = T * blockIdx.x / gridDim.x;
   const int64_t t1 = T * (blockIdx.x + 1) / gridDim.x;
 
   int seg = -1;
   const InstDev *Ip = nullptr;
   InstState *Sp = nullptr;
-  int sp = 0, buf = 0, N = 0;
+  int sp = 0, N = 0;
   int64_t k = 0, ext = 0, seg_first = 0;
   typename F::View P;
-  int64_t *A_out = nullptr;     // deposit target (HBM) of this segment
-  int64_t *A_next_other = nullptr;
+  int64_t *A_out = nullptr;
+  int *gq = nullptr;
   bool deposit_on = false;
   unsigned long long live_here = 0;
 
+  // Append this lane's entry (if any) to the wavefront queue; move full
+  // groups of 64 (or, at the end of a segment, all) to the segment's HBM queue.
+  auto enqueue = [&](bool want, int entry) {
+    const unsigned long long m = __ballot(want);
+    if (want) wq[wq_n + __popcll(m & lt_mask)] = entry;
+    wq_n += __popcll(m);
+  };
+  auto spill = [&](bool all) {
+    while (wq_n >= 64 || (all && wq_n > 0)) {
+      const int n = wq_n < 64 ? wq_n : 64;
+      unsigned long long b = 0;
+      if (lane == 0) b = atomicAdd(&Sp->qcount[sp], (unsigned long long)n);
+      b = __shfl(b, 0, 64);
+      if (lane < n) gq[b + lane] = wq[wq_n - n + lane];
+      wq_n -= n;
+    }
+  };
   auto flush = [&]() {
-    // Deposit: nonzero LDS entries -> HBM (periodic: node N folds into 0).
+    spill(true);
     __syncthreads();
     if (deposit_on) {
       if (Ip->bc == 1 && t == 0) {
@@ -481,31 +594,13 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
         }
       }
     }
-    // Live count of this segment (particle-steps) and the shared counters.
     const unsigned long long lw = wave_sum_u64<64>(live_here);
-    if (__lane_id() == 0 && lw) atomicAdd(&sm.ctr[C_PSTEPS], lw);
+    if (lane == 0 && lw) atomicAdd(&sm.ctr[C_PSTEPS], lw);
     live_here = 0;
-    __syncthreads();
-    if (t < kNctr) {
-      const unsigned long long v = sm.ctr[t];
-      if (v) {
-        if (t == C_PSTEPS && MODE != M_DEPOSIT && MODE != M_MCC && MODE != M_PULLBACK) {
-          atomicAdd(&Sp->ctr[C_PSTEPS], v);
-          atomicAdd(&Sp->step_live[sp], v);
-        } else if (t >= C_ABS && t < C_ABS + 4) {
-          atomicAdd(&Sp->ctr[t], v);
-          atomicAdd(&Sp->step_absorbed[(t - C_ABS) >> 1], v);
-        } else if (t != C_PSTEPS) {
-          atomicAdd(&Sp->ctr[t], v);
-        }
-        sm.ctr[t] = 0;
-      }
-    }
-    __syncthreads();
+    flush_counters<BLOCK>(sm, Sp, sp);
   };
 
   for (int64_t tile = t0; tile < t1; ++tile) {
-    // Segment of this tile (uniform across the workgroup).
     int s = seg < 0 ? 0 : seg;
     while (sm.seg_prefix[s + 1] <= tile) ++s;
     s = __builtin_amdgcn_readfirstlane(s);
@@ -518,63 +613,59 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
       const InstDev &I = *Ip;
       N = I.N;
       k = Sp->k;
-      buf = Sp->parity;
       ext = Sp->extent[sp];
       seg_first = sm.seg_prefix[seg];
-      P = F::view(I, sp, buf);
+      P = F::view(I, sp, Sp->parity);
+      gq = I.queue[sp];
       const int par = (int)(k & 1);
       deposit_on = (MODE == M_DEPOSIT) || (MODE == M_FUSED);
       A_out = (MODE == M_DEPOSIT) ? I.A[par][sp] : I.A[par ^ 1][sp];
-      A_next_other = I.A[par ^ 1][sp ^ 1];
-      // Stage the gather tables.
-      if constexpr (F::prec == 1) {
-        if (MODE != M_DEPOSIT && MODE != M_MCC) {
-          const int ne = (I.gather == 0) ? N : N + 1;
-          for (int j = t; j < ne; j += BLOCK) sE32[j] = I.E32[j];
-          if (!I.uniform) {
-            for (int j = t; j < N; j += BLOCK) {
-              sDtoh[j] = I.dtoh32[j];
-              sRf[j] = I.rf32[j];
-              sRb[j] = I.rb32[j];
+      if (MODE != M_MCC) {
+        const int ne = (I.gather == 0) ? N : N + 1;
+        if constexpr (F::prec == 1) {
+          if (MODE != M_DEPOSIT) {
+            for (int j = t; j < ne; j += BLOCK) sE32[j] = I.E32[j];
+            if (!I.uniform) {
+              for (int j = t; j < N; j += BLOCK) {
+                sDtoh[j] = I.dtoh32[j];
+                sRf[j] = I.rf32[j];
+                sRb[j] = I.rb32[j];
+                sRun[j] = I.runs[j];
+              }
             }
           }
-        }
-      } else {
-        if (MODE != M_MCC) {
-          const int ne = (I.gather == 0) ? N : N + 1;
+        } else {
           if (MODE != M_DEPOSIT)
             for (int j = t; j < ne; j += BLOCK) sE64[j] = I.E64[j];
-          if (!I.uniform) {
+          if (!I.uniform)
             for (int j = t; j <= N; j += BLOCK) sNodes[j] = I.nodes[j];
-            for (int j = t; j < N; j += BLOCK) sH[j] = I.h[j];
-          }
         }
       }
       __syncthreads();
     }
     const InstDev &I = *Ip;
-    InstState &S = *Sp;
     const int64_t base = (tile - seg_first) * TILE;
     const int64_t i0 = base + (int64_t)t * kPPT;
     const bool full = i0 + kPPT <= ext;
     const bool due_eedf = (MODE == M_PUSH || MODE == M_FUSED) && sp == 0 && eedf_due(I, k);
-    const double nudt = I.nudt[sp];
+    const bool coll = (MODE == M_MCC || MODE == M_FUSED) && I.nudt[sp] > 0.0;
     DepAcc dep;
     dep.init();
+    bool want[kPPT];
+    int went[kPPT];
 
     if constexpr (F::prec == 1) {
       // ---------------- FP32-state form ----------------
-      int c[kPPT];
+      int c[kPPT], kn[kPPT];
       float o[kPPT], vx[kPPT];
-      int kn[kPPT];
       if (full) {
         const int4 c4 = *reinterpret_cast<const int4 *>(P.cell + i0);
         c[0] = c4.x; c[1] = c4.y; c[2] = c4.z; c[3] = c4.w;
-        {
+        if (MODE != M_MCC) {
           const float4 o4 = *reinterpret_cast<const float4 *>(P.off + i0);
           o[0] = o4.x; o[1] = o4.y; o[2] = o4.z; o[3] = o4.w;
         }
-        if (MODE != M_DEPOSIT) {
+        if (MODE != M_DEPOSIT && MODE != M_MCC) {
           const float4 v4 = *reinterpret_cast<const float4 *>(P.vx + i0);
           vx[0] = v4.x; vx[1] = v4.y; vx[2] = v4.z; vx[3] = v4.w;
         }
@@ -594,29 +685,28 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
         }
       }
       int cn[kPPT];
-      float on[kPPT];
-      float vn[kPPT];
+      float on[kPPT], vn[kPPT];
 #pragma unroll
       for (int q = 0; q < kPPT; ++q) {
+        want[q] = false;
+        went[q] = 0;
         cn[q] = c[q];
         on[q] = o[q];
         vn[q] = vx[q];
         if (c[q] < 0) continue;   // dead slot
-        const int64_t i = i0 + q;
+        const int ii = (int)(i0 + q);
         if constexpr (MODE == M_DEPOSIT) {
           int64_t w0, w1;
-          weights((double)o[q], w0, w1);
+          weights32(o[q], w0, w1);
           dep.add(sA, c[q], w0, w1);
-          continue;
-        }
-        if constexpr (MODE == M_PULLBACK) {
+        } else if constexpr (MODE == M_PULLBACK) {
           const float e = (I.gather == 0) ? sE32[c[q]]
                                           : ((1.0f - o[q]) * sE32[c[q]]) + (o[q] * sE32[c[q] + 1]);
           vn[q] = vx[q] - I.hq32[sp] * e;
-          continue;
-        }
-        bool alive = true;
-        if constexpr (MODE == M_PUSH || MODE == M_FUSED) {
+        } else if constexpr (MODE == M_MCC) {
+          want[q] = coll && kn[q] <= k;
+          went[q] = qentry(ii, 0);
+        } else {
           live_here += 1;
           const int j = c[q];
           const float e = (I.gather == 0) ? sE32[j]
@@ -625,93 +715,37 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
           const float dtoh = I.uniform ? I.dtoh32u : sDtoh[j];
           float sig = o[q] + v1 * dtoh;
           int jj = j;
-          const int wall = walk32(I, sRf, sRb, jj, sig);
+          const int wall = walk32(I, sRf, sRb, sRun, jj, sig);
           vn[q] = v1;
           if (wall != 0 || v1 != v1) {
-            alive = false;
             cn[q] = -1;
-            if (wall == 2 || v1 != v1) {
-              set_status(S, ST_NONFINITE);
-              atomicAdd(&sm.ctr[C_NONFINITE], 1ull);
-            } else {
-              const int wi = wall < 0 ? 0 : 1;
-              atomicAdd(&sm.ctr[C_ABS + 2 * sp + wi], 1ull);
-              const double vy = (double)P.vy[i], vz = (double)P.vz[i], vxd = (double)v1;
-              const double en = (0.5 * I.mass[sp] / kQE) * ((vxd * vxd + vy * vy) + vz * vz);
-              atomicAdd(&sm.ctr[C_EABS + 2 * sp + wi], (unsigned long long)rint(en * 65536.0));
-              if (sp == 1 && I.gamma_see > 0.0 && I.nsp > 1)
-                emit_secondary<F>(I, S, sm, P.id[i], wall, k, buf, MODE == M_FUSED,
-                                  I.A[(k + 1) & 1][0]);
-            }
+            want[q] = true;
+            went[q] = qentry(ii, (wall == 2 || v1 != v1) ? 3 : (wall < 0 ? 1 : 2));
           } else {
             cn[q] = jj;
             on[q] = sig;
+            if (MODE == M_FUSED && coll && kn[q] <= k) {
+              want[q] = true;
+              went[q] = qentry(ii, 0);
+            }
             if (due_eedf) {
               const double x = I.uniform ? ((double)jj * I.dx + (double)sig * I.dx)
                                          : (I.nodes[jj] + (double)sig * I.h[jj]);
               if (fabs(x - I.eedf_centre) < I.eedf_half)
-                eedf_sample(I, x, (double)v1, (double)P.vy[i], (double)P.vz[i]);
+                eedf_sample(I, x, (double)v1, (double)P.vy[ii], (double)P.vz[ii]);
             }
-          }
-        }
-        if constexpr (MODE == M_MCC || MODE == M_FUSED) {
-          if (alive && nudt > 0.0 && kn[q] <= k) {
-            const uint64_t id = P.id[i];
-            double ux = (double)vn[q], uy = (double)P.vy[i], uz = (double)P.vz[i];
-            bool bound = false;
-            atomicAdd(&sm.ctr[C_CAND + sp], 1ull);
-            if (sp == 0) {
-              double ej[3];
-              const int proc = collide_electron(I, id, k, ux, uy, uz, bound, ej);
-              if (proc) atomicAdd(&sm.ctr[proc == 1 ? C_EL : (proc == 2 ? C_EX : C_IZ)], 1ull);
-              if (proc == 3 && I.nsp > 1) {
-                const uint4 ch = philox((uint32_t)k, TAG_CHILD, I.seed, id);
-                const uint64_t eid = (uint64_t)ch.x | ((uint64_t)ch.y << 32);
-                const uint64_t iid = (uint64_t)ch.z | ((uint64_t)ch.w << 32);
-                double gx, gy, gz;
-                gas_velocity(I, id, k, 0, gx, gy, gz);
-                const int64_t ie = append_slot(I, S, 0);
-                const int64_t ii = append_slot(I, S, 1);
-                const int cc = cn[q];
-                const float oo = on[q];
-                if (ie >= 0)
-                  write_new<F>(I, P, ie, 0.0, cc, oo, ej[0], ej[1], ej[2], eid,
-                               next_candidate(eid, k, 0, I.seed, I.nudt[0]));
-                if (ii >= 0)
-                  write_new<F>(I, F::view(I, 1, buf), ii, 0.0, cc, oo, gx, gy, gz, iid,
-                               next_candidate(iid, k, 1, I.seed, I.nudt[1]));
-                if constexpr (MODE == M_FUSED) {
-                  int64_t w0, w1;
-                  weights((double)oo, w0, w1);
-                  if (ie >= 0) {
-                    atomicAdd(reinterpret_cast<unsigned long long *>(&sA[cc]), (unsigned long long)w0);
-                    atomicAdd(reinterpret_cast<unsigned long long *>(&sA[cc + 1]), (unsigned long long)w1);
-                  }
-                  if (ii >= 0) global_deposit(A_next_other, cc, w0, w1);
-                }
-              }
-            } else {
-              if (collide_ion(I, id, k, ux, uy, uz, bound)) atomicAdd(&sm.ctr[C_CX], 1ull);
+            if constexpr (MODE == M_FUSED) {
+              int64_t w0, w1;
+              weights32(sig, w0, w1);
+              dep.add(sA, jj, w0, w1);
             }
-            if (bound) atomicAdd(&sm.ctr[C_BOUND], 1ull);
-            vn[q] = (float)ux;
-            P.vy[i] = (float)uy;
-            P.vz[i] = (float)uz;
-            P.knext[i] = next_candidate(id, k, sp, I.seed, nudt);
-          }
-        }
-        if constexpr (MODE == M_FUSED) {
-          if (alive) {
-            int64_t w0, w1;
-            weights((double)on[q], w0, w1);
-            dep.add(sA, cn[q], w0, w1);
           }
         }
       }
-      // Write back the streamed fields.
-      if constexpr (MODE != M_DEPOSIT) {
+      if constexpr (MODE == M_DEPOSIT || MODE == M_FUSED) deposit_wave(sA, dep.has, dep.key, dep.a0, dep.a1);
+      if constexpr (MODE == M_PUSH || MODE == M_FUSED || MODE == M_PULLBACK) {
         if (full) {
-          if constexpr (MODE == M_PUSH || MODE == M_FUSED) {
+          if constexpr (MODE != M_PULLBACK) {
             *reinterpret_cast<int4 *>(P.cell + i0) = make_int4(cn[0], cn[1], cn[2], cn[3]);
             *reinterpret_cast<float4 *>(P.off + i0) = make_float4(on[0], on[1], on[2], on[3]);
           }
@@ -721,7 +755,7 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
           for (int q = 0; q < kPPT; ++q) {
             const int64_t i = i0 + q;
             if (i < ext) {
-              if constexpr (MODE == M_PUSH || MODE == M_FUSED) {
+              if constexpr (MODE != M_PULLBACK) {
                 P.cell[i] = cn[q];
                 P.off[i] = on[q];
               }
@@ -738,7 +772,7 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
         const double2 xa = *reinterpret_cast<const double2 *>(P.x + i0);
         const double2 xb = *reinterpret_cast<const double2 *>(P.x + i0 + 2);
         x[0] = xa.x; x[1] = xa.y; x[2] = xb.x; x[3] = xb.y;
-        if (MODE != M_DEPOSIT) {
+        if (MODE != M_DEPOSIT && MODE != M_MCC) {
           const double2 va = *reinterpret_cast<const double2 *>(P.vx + i0);
           const double2 vb = *reinterpret_cast<const double2 *>(P.vx + i0 + 2);
           vx[0] = va.x; vx[1] = va.y; vx[2] = vb.x; vx[3] = vb.y;
@@ -758,34 +792,32 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
         }
       }
       double xn[kPPT], vn[kPPT];
-      const double *nodes = sNodes;
-      const double *hh = sH;
 #pragma unroll
       for (int q = 0; q < kPPT; ++q) {
+        want[q] = false;
+        went[q] = 0;
         xn[q] = x[q];
         vn[q] = vx[q];
         if (!(x[q] >= 0.0)) continue;   // dead slot
-        const int64_t i = i0 + q;
+        const int ii = (int)(i0 + q);
         if constexpr (MODE == M_DEPOSIT) {
           double xi;
-          const int j = locate64(I, nodes, hh, x[q], xi);
+          const int j = locate64(I, sNodes, x[q], xi);
           int64_t w0, w1;
           weights(xi, w0, w1);
           dep.add(sA, j, w0, w1);
-          continue;
-        }
-        if constexpr (MODE == M_PULLBACK) {
+        } else if constexpr (MODE == M_PULLBACK) {
           double xi;
-          const int j = locate64(I, nodes, hh, x[q], xi);
+          const int j = locate64(I, sNodes, x[q], xi);
           const double e = (I.gather == 0) ? sE64[j] : (1.0 - xi) * sE64[j] + xi * sE64[j + 1];
           vn[q] = vx[q] - I.hq[sp] * e;
-          continue;
-        }
-        bool alive = true;
-        if constexpr (MODE == M_PUSH || MODE == M_FUSED) {
+        } else if constexpr (MODE == M_MCC) {
+          want[q] = coll && kn[q] <= k;
+          went[q] = qentry(ii, 0);
+        } else {
           live_here += 1;
           double xi;
-          const int j = locate64(I, nodes, hh, x[q], xi);
+          const int j = locate64(I, sNodes, x[q], xi);
           const double e = (I.gather == 0) ? sE64[j] : (1.0 - xi) * sE64[j] + xi * sE64[j + 1];
           const double v1 = vx[q] + I.qmdt[sp] * e;
           double x1 = x[q] + v1 * I.dt;
@@ -801,87 +833,31 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
             wall = (x1 < 0.0) ? -1 : ((x1 >= I.L) ? 1 : 2);
           }
           if (wall != 0) {
-            alive = false;
             xn[q] = -1.0;
-            if (wall == 2) {
-              set_status(S, ST_NONFINITE);
-              atomicAdd(&sm.ctr[C_NONFINITE], 1ull);
-            } else {
-              const int wi = wall < 0 ? 0 : 1;
-              atomicAdd(&sm.ctr[C_ABS + 2 * sp + wi], 1ull);
-              const double vy = P.vy[i], vz = P.vz[i];
-              const double en = (0.5 * I.mass[sp] / kQE) * ((v1 * v1 + vy * vy) + vz * vz);
-              atomicAdd(&sm.ctr[C_EABS + 2 * sp + wi], (unsigned long long)rint(en * 65536.0));
-              if (sp == 1 && I.gamma_see > 0.0 && I.nsp > 1)
-                emit_secondary<F>(I, S, sm, P.id[i], wall, k, buf, MODE == M_FUSED,
-                                  I.A[(k + 1) & 1][0]);
-            }
+            want[q] = true;
+            went[q] = qentry(ii, (wall == 2) ? 3 : (wall < 0 ? 1 : 2));
           } else {
             xn[q] = x1;
-            if (due_eedf && fabs(x1 - I.eedf_centre) < I.eedf_half)
-              eedf_sample(I, x1, v1, P.vy[i], P.vz[i]);
-          }
-        }
-        if constexpr (MODE == M_MCC || MODE == M_FUSED) {
-          if (alive && nudt > 0.0 && kn[q] <= k) {
-            const uint64_t id = P.id[i];
-            double ux = vn[q], uy = P.vy[i], uz = P.vz[i];
-            bool bound = false;
-            atomicAdd(&sm.ctr[C_CAND + sp], 1ull);
-            if (sp == 0) {
-              double ej[3];
-              const int proc = collide_electron(I, id, k, ux, uy, uz, bound, ej);
-              if (proc) atomicAdd(&sm.ctr[proc == 1 ? C_EL : (proc == 2 ? C_EX : C_IZ)], 1ull);
-              if (proc == 3 && I.nsp > 1) {
-                const uint4 ch = philox((uint32_t)k, TAG_CHILD, I.seed, id);
-                const uint64_t eid = (uint64_t)ch.x | ((uint64_t)ch.y << 32);
-                const uint64_t iid = (uint64_t)ch.z | ((uint64_t)ch.w << 32);
-                double gx, gy, gz;
-                gas_velocity(I, id, k, 0, gx, gy, gz);
-                const int64_t ie = append_slot(I, S, 0);
-                const int64_t ii = append_slot(I, S, 1);
-                const double xx = xn[q];
-                if (ie >= 0)
-                  write_new<F>(I, P, ie, xx, 0, 0.0f, ej[0], ej[1], ej[2], eid,
-                               next_candidate(eid, k, 0, I.seed, I.nudt[0]));
-                if (ii >= 0)
-                  write_new<F>(I, F::view(I, 1, buf), ii, xx, 0, 0.0f, gx, gy, gz, iid,
-                               next_candidate(iid, k, 1, I.seed, I.nudt[1]));
-                if constexpr (MODE == M_FUSED) {
-                  double xi;
-                  const int j = locate64(I, nodes, hh, xx, xi);
-                  int64_t w0, w1;
-                  weights(xi, w0, w1);
-                  if (ie >= 0) {
-                    atomicAdd(reinterpret_cast<unsigned long long *>(&sA[j]), (unsigned long long)w0);
-                    atomicAdd(reinterpret_cast<unsigned long long *>(&sA[j + 1]), (unsigned long long)w1);
-                  }
-                  if (ii >= 0) global_deposit(A_next_other, j, w0, w1);
-                }
-              }
-            } else {
-              if (collide_ion(I, id, k, ux, uy, uz, bound)) atomicAdd(&sm.ctr[C_CX], 1ull);
+            if (MODE == M_FUSED && coll && kn[q] <= k) {
+              want[q] = true;
+              went[q] = qentry(ii, 0);
             }
-            if (bound) atomicAdd(&sm.ctr[C_BOUND], 1ull);
-            vn[q] = ux;
-            P.vy[i] = uy;
-            P.vz[i] = uz;
-            P.knext[i] = next_candidate(id, k, sp, I.seed, nudt);
-          }
-        }
-        if constexpr (MODE == M_FUSED) {
-          if (alive) {
-            double xi;
-            const int j = locate64(I, nodes, hh, xn[q], xi);
-            int64_t w0, w1;
-            weights(xi, w0, w1);
-            dep.add(sA, j, w0, w1);
+            if (due_eedf && fabs(x1 - I.eedf_centre) < I.eedf_half)
+              eedf_sample(I, x1, v1, P.vy[ii], P.vz[ii]);
+            if constexpr (MODE == M_FUSED) {
+              double xi1;
+              const int j1 = locate64(I, sNodes, x1, xi1);
+              int64_t w0, w1;
+              weights(xi1, w0, w1);
+              dep.add(sA, j1, w0, w1);
+            }
           }
         }
       }
-      if constexpr (MODE != M_DEPOSIT) {
+      if constexpr (MODE == M_DEPOSIT || MODE == M_FUSED) deposit_wave(sA, dep.has, dep.key, dep.a0, dep.a1);
+      if constexpr (MODE == M_PUSH || MODE == M_FUSED || MODE == M_PULLBACK) {
         if (full) {
-          if constexpr (MODE == M_PUSH || MODE == M_FUSED) {
+          if constexpr (MODE != M_PULLBACK) {
             *reinterpret_cast<double2 *>(P.x + i0) = make_double2(xn[0], xn[1]);
             *reinterpret_cast<double2 *>(P.x + i0 + 2) = make_double2(xn[2], xn[3]);
           }
@@ -892,33 +868,158 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
           for (int q = 0; q < kPPT; ++q) {
             const int64_t i = i0 + q;
             if (i < ext) {
-              if constexpr (MODE == M_PUSH || MODE == M_FUSED) P.x[i] = xn[q];
+              if constexpr (MODE != M_PULLBACK) P.x[i] = xn[q];
               P.vx[i] = vn[q];
             }
           }
         }
       }
     }
-    if constexpr (MODE == M_DEPOSIT || MODE == M_FUSED) {
-      deposit_wave(sA, dep.has, dep.key, dep.a0, dep.a1);
+    if constexpr (MODE == M_PUSH || MODE == M_MCC || MODE == M_FUSED) {
+#pragma unroll
+      for (int q = 0; q < kPPT; ++q) enqueue(want[q], went[q]);
+      spill(false);
     }
   }
   if (seg >= 0) flush();
+}
 
-  // The last workgroup to finish closes the step: new particles join the
-  // extents, the live count is updated and checked, and k advances.
-  if constexpr (MODE == M_MCC || MODE == M_FUSED) {
+// Handle one queued particle: absorption (tallies, secondary emission) or a
+// null-collision candidate (collision, ionisation products, next candidate
+// step).  Products go straight into the deposit of step k+1 in the fused pass.
+template <class F, int MODE>
+__device__ void drain_one(const InstDev &I, InstState &S, Smem &sm, int sp, int buf, int64_t k,
+                          typename F::View P, int entry) {
+  const int64_t i = entry & kQMask;
+  const int kind = (int)((unsigned)entry >> kQShift);
+  if (kind == 3) {
+    set_status(S, ST_NONFINITE);
+    atomicAdd(&sm.ctr[C_NONFINITE], 1ull);
+    return;
+  }
+  const double vxd = (double)P.vx[i], vy = (double)P.vy[i], vz = (double)P.vz[i];
+  if (kind != 0) {
+    const int wi = kind - 1;
+    atomicAdd(&sm.ctr[C_ABS + 2 * sp + wi], 1ull);
+    const double en = (0.5 * I.mass[sp] / kQE) * ((vxd * vxd + vy * vy) + vz * vz);
+    atomicAdd(&sm.ctr[C_EABS + 2 * sp + wi], (unsigned long long)rint(en * 65536.0));
+    if (sp == 1 && I.gamma_see > 0.0 && I.nsp > 1)
+      emit_secondary<F>(I, S, sm, P.id[i], wi == 0 ? -1 : 1, k, buf, MODE == M_FUSED,
+                        I.A[(k + 1) & 1][0]);
+    return;
+  }
+  const uint64_t id = P.id[i];
+  double ux = vxd, uy = vy, uz = vz;
+  bool bound = false;
+  atomicAdd(&sm.ctr[C_CAND + sp], 1ull);
+  if (sp == 0) {
+    double ej[3];
+    const int proc = collide_electron(I, id, k, ux, uy, uz, bound, ej);
+    if (proc) atomicAdd(&sm.ctr[proc == 1 ? C_EL : (proc == 2 ? C_EX : C_IZ)], 1ull);
+    if (proc == 3 && I.nsp > 1) {
+      const uint4 ch = philox((uint32_t)k, TAG_CHILD, I.seed, id);
+      const uint64_t eid = (uint64_t)ch.x | ((uint64_t)ch.y << 32);
+      const uint64_t iid = (uint64_t)ch.z | ((uint64_t)ch.w << 32);
+      double gx, gy, gz;
+      gas_velocity(I, id, k, 0, gx, gy, gz);
+      const int64_t ie = append_slot(I, S, 0);
+      const int64_t ii = append_slot(I, S, 1);
+      int cc = 0;
+      float oo = 0.0f;
+      double xx = 0.0;
+      if constexpr (F::prec == 1) {
+        cc = P.cell[i];
+        oo = P.off[i];
+      } else {
+        xx = P.x[i];
+      }
+      if (ie >= 0)
+        write_new<F>(I, P, ie, xx, cc, oo, ej[0], ej[1], ej[2], eid,
+                     next_candidate(eid, k, 0, I.seed, I.nudt[0]));
+      if (ii >= 0)
+        write_new<F>(I, F::view(I, 1, buf), ii, xx, cc, oo, gx, gy, gz, iid,
+                     next_candidate(iid, k, 1, I.seed, I.nudt[1]));
+      if constexpr (MODE == M_FUSED) {
+        int j;
+        double xi;
+        if constexpr (F::prec == 1) {
+          j = cc;
+          xi = (double)oo;
+        } else {
+          j = locate64(I, I.nodes, xx, xi);
+        }
+        int64_t w0, w1;
+        weights(xi, w0, w1);
+        const int par1 = (int)((k + 1) & 1);
+        if (ie >= 0) global_deposit(I.A[par1][0], j, w0, w1);
+        if (ii >= 0) global_deposit(I.A[par1][1], j, w0, w1);
+      }
+    }
+  } else {
+    if (collide_ion(I, id, k, ux, uy, uz, bound)) atomicAdd(&sm.ctr[C_CX], 1ull);
+  }
+  if (bound) atomicAdd(&sm.ctr[C_BOUND], 1ull);
+  if constexpr (F::prec == 1) {
+    P.vx[i] = (float)ux;
+    P.vy[i] = (float)uy;
+    P.vz[i] = (float)uz;
+  } else {
+    P.vx[i] = ux;
+    P.vy[i] = uy;
+    P.vz[i] = uz;
+  }
+  P.knext[i] = next_candidate(id, k, sp, I.seed, I.nudt[sp]);
+}
+
+// Drain the per-segment queues with full wavefronts; in the modes that end a
+// step the last workgroup to finish also closes the step: new particles join
+// the extents, the live count is updated and checked, and k advances.
+template <class F, int MODE>
+__global__ void __launch_bounds__(256)
+k_drain(const InstDev *__restrict__ insts, InstState *__restrict__ states, int n_inst,
+        unsigned int *__restrict__ done) {
+  constexpr int BLOCK = 256;
+  __shared__ Smem sm;
+  const int t = threadIdx.x;
+  if (t < kNctr) sm.ctr[t] = 0;
+  const int64_t T = segment_prefix<BLOCK>(insts, states, n_inst, BLOCK, sm.seg_prefix,
+                                          [](const InstState &S, int sp) { return (int64_t)S.qcount[sp]; });
+  const int64_t t0 = T * blockIdx.x / gridDim.x;
+  const int64_t t1 = T * (blockIdx.x + 1) / gridDim.x;
+  int seg = -1;
+  InstState *Sp = nullptr;
+  for (int64_t tile = t0; tile < t1; ++tile) {
+    int s = seg < 0 ? 0 : seg;
+    while (sm.seg_prefix[s + 1] <= tile) ++s;
+    s = __builtin_amdgcn_readfirstlane(s);
+    if (s != seg) {
+      if (seg >= 0) flush_counters<BLOCK>(sm, Sp, seg & 1);
+      seg = s;
+      Sp = &states[seg >> 1];
+    }
+    const InstDev &I = insts[seg >> 1];
+    const int sp = seg & 1;
+    const int64_t e = (tile - sm.seg_prefix[seg]) * BLOCK + t;
+    if (e < (int64_t)Sp->qcount[sp]) {
+      const int buf = Sp->parity;
+      drain_one<F, MODE>(I, *Sp, sm, sp, buf, Sp->k, F::view(I, sp, buf), I.queue[sp][e]);
+    }
+  }
+  if (seg >= 0) flush_counters<BLOCK>(sm, Sp, seg & 1);
+
+  __threadfence();
+  __syncthreads();
+  if (t == 0) sm.is_last = (atomicAdd(done, 1u) == gridDim.x - 1);
+  __syncthreads();
+  if (sm.is_last) {
     __threadfence();
-    __syncthreads();
-    if (t == 0) sm.is_last = (atomicAdd(done, 1u) == gridDim.x - 1);
-    __syncthreads();
-    if (sm.is_last) {
-      __threadfence();
-      for (int i = t; i < n_inst; i += BLOCK) {
-        const InstDev &I = insts[i];
-        InstState &S = states[i];
-        if (!I.active || S.frozen != 0 || (I.k_stop > 0 && S.k >= I.k_stop)) continue;
-        for (int s = 0; s < I.nsp; ++s) {
+    for (int i = t; i < n_inst; i += BLOCK) {
+      const InstDev &I = insts[i];
+      InstState &S = states[i];
+      if (!I.active || S.frozen != 0 || (I.k_stop > 0 && S.k >= I.k_stop)) continue;
+      for (int s = 0; s < I.nsp; ++s) {
+        S.qcount[s] = 0;
+        if constexpr (MODE == M_MCC || MODE == M_FUSED) {
           const unsigned long long app = atomicAdd(&S.append[s], 0ull);
           const unsigned long long lv = atomicAdd(&S.step_live[s], 0ull);
           const unsigned long long ab = atomicAdd(&S.step_absorbed[s], 0ull);
@@ -934,11 +1035,13 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
           S.step_live[s] = 0;
           S.step_absorbed[s] = 0;
         }
+      }
+      if constexpr (MODE == M_MCC || MODE == M_FUSED) {
         S.k += 1;
         if (atomicOr(&S.status, 0) != 0) S.frozen = 1;
       }
-      if (t == 0) *done = 0u;
     }
+    if (t == 0) *done = 0u;
   }
 }
 
@@ -1029,19 +1132,48 @@ __global__ void k_zero_deposit(const InstDev *__restrict__ insts, const InstStat
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-size_t particle_lds_bytes(int prec, int max_n) {
+size_t particle_lds_bytes(int prec, int max_n, int block) {
   const size_t np1 = (size_t)max_n + 1;
-  if (prec == 1) return np1 * 8 + np1 * 4 + 3 * (size_t)max_n * 4;
-  return np1 * 8 + np1 * 8 + np1 * 8 + (size_t)max_n * 8;
+  const size_t tables = (prec == 1) ? np1 * 12 + (size_t)max_n * 16 : np1 * 24;
+  const size_t q = (size_t)(block / 64) * kWaveQ * sizeof(int);
+  return ((tables + 15) & ~(size_t)15) + q;
 }
 
 template <class F, int MODE, int BLOCK>
 static hipError_t launch_pk(const InstDev *insts, InstState *states, int n_inst, int grid,
                             int max_n, unsigned int *done, hipStream_t s) {
-  const size_t lds = particle_lds_bytes(F::prec, max_n);
+  const size_t lds = particle_lds_bytes(F::prec, max_n, BLOCK);
   hipLaunchKernelGGL((k_particles<F, MODE, BLOCK>), dim3(grid), dim3(BLOCK), lds, s, insts, states,
-                     n_inst, max_n, done);
+                     n_inst, max_n);
+  (void)done;
   return hipGetLastError();
+}
+
+template <class F>
+static hipError_t launch_drain_form(const InstDev *insts, InstState *states, int n_inst, int mode,
+                                    int grid, unsigned int *done, hipStream_t s) {
+  switch (mode) {
+    case M_PUSH:
+      hipLaunchKernelGGL((k_drain<F, M_PUSH>), dim3(grid), dim3(256), 0, s, insts, states, n_inst, done);
+      break;
+    case M_MCC:
+      hipLaunchKernelGGL((k_drain<F, M_MCC>), dim3(grid), dim3(256), 0, s, insts, states, n_inst, done);
+      break;
+    case M_FUSED:
+      hipLaunchKernelGGL((k_drain<F, M_FUSED>), dim3(grid), dim3(256), 0, s, insts, states, n_inst, done);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// The number of queued particles is only known on the device, so the drain
+// grid is fixed and its workgroups split whatever the queues hold.
+hipError_t launch_drain(const InstDev *insts, InstState *states, int n_inst, int prec, int mode,
+                        int grid, unsigned int *done, hipStream_t s) {
+  if (prec == 1) return launch_drain_form<F32>(insts, states, n_inst, mode, grid, done, s);
+  return launch_drain_form<F64>(insts, states, n_inst, mode, grid, done, s);
 }
 
 template <class F>
@@ -1049,8 +1181,8 @@ static hipError_t launch_form(const InstDev *insts, InstState *states, int n_ins
                               int block, int grid, int max_n, unsigned int *done, hipStream_t s) {
   if (mode == M_FUSED && block == 512)
     return launch_pk<F, M_FUSED, 512>(insts, states, n_inst, grid, max_n, done, s);
-  if (mode == M_FUSED && block == 128)
-    return launch_pk<F, M_FUSED, 128>(insts, states, n_inst, grid, max_n, done, s);
+  if (mode == M_FUSED && block == 1024)
+    return launch_pk<F, M_FUSED, 1024>(insts, states, n_inst, grid, max_n, done, s);
   switch (mode) {
     case M_DEPOSIT: return launch_pk<F, M_DEPOSIT, 256>(insts, states, n_inst, grid, max_n, done, s);
     case M_PUSH: return launch_pk<F, M_PUSH, 256>(insts, states, n_inst, grid, max_n, done, s);

@@ -163,3 +163,79 @@ def test_periodic_wrap_fp64_and_fp32():
                                    g.walk_tables(dt))
     assert np.all(wall == 0)
     assert np.allclose(g.position(cell, off), [0.008, 0.001], atol=1e-9)
+
+
+def collapsed_walk(cell, sig, rf, rb, runs_lo, runs_hi, N):
+    """Run-collapsed form of the FP32 walk (what the GPU kernel executes):
+    inside a run of equal cells m steps become one FP32 operation."""
+    one = np.float32(1.0)
+    j = int(cell)
+    s = np.float32(sig)
+    while s < 0:
+        lo = runs_lo[j]
+        if lo < j:
+            m = np.float32(-np.floor(s))
+            avail = j - lo
+            if m <= avail:
+                j -= int(m)
+                s = np.float32(s + m)
+                continue
+            s = np.float32(s + np.float32(avail))
+            j = lo
+        j -= 1
+        if j < 0:
+            return j, s, -1
+        s = np.float32(one + np.float32(s * rb[j]))
+    while s >= one:
+        hi = runs_hi[j]
+        if hi > j:
+            m = np.float32(np.floor(s))
+            avail = hi - j
+            if m <= avail:
+                j += int(m)
+                s = np.float32(s - m)
+                continue
+            s = np.float32(s - np.float32(avail))
+            j = hi
+        s = np.float32(np.float32(s - one) * rf[j])
+        j += 1
+        if j >= N:
+            return j, s, 1
+    return j, s, 0
+
+
+def test_run_collapsed_walk_equals_cell_walk_bitwise():
+    """The refined grid of Section 3c consists of long runs of equal cells;
+    collapsing the unit-ratio steps of a run must not change a single bit."""
+    from oracle.grid import refined_nodes
+    L = 0.03
+    nodes = refined_nodes(L, L / 1024, L / 128, 0.004)
+    N = len(nodes) - 1
+    g = Grid.make(L, N, nodes)
+    dtoh, rf, rb = g.walk_tables(1e-10)
+    lo = np.zeros(N, int)
+    hi = np.zeros(N, int)
+    j = 0
+    while j < N:
+        e = j
+        while e + 1 < N and rf[e] == 1.0 and rb[e] == 1.0:
+            e += 1
+        lo[j:e + 1] = j
+        hi[j:e + 1] = e
+        j = e + 1
+    assert (hi - lo).max() > 50
+    r = inputs.rng(25)
+    n = 20000
+    cell = r.integers(0, N, n).astype(np.int32)
+    sig = np.concatenate([r.uniform(-300, 300, n - 2000), -(10.0 ** r.uniform(-10, 0, 1000)),
+                          r.uniform(0.999, 1.0, 1000)]).astype(np.float32)
+    sp = Species(s=0, prec=FP32, vx=np.zeros(n, np.float32), vy=np.zeros(n, np.float32),
+                 vz=np.zeros(n, np.float32), id=np.arange(n, dtype=np.uint64),
+                 knext=np.zeros(n, np.int64), cell=cell, off=sig)
+    zero = np.zeros(N, np.float32)
+    _, c1, o1, w1 = push_fp32(g, sp, zero, 0, np.float32(0.0), (zero, rf, rb))
+    for i in range(n):
+        jj, ss, ww = collapsed_walk(cell[i], sig[i], rf, rb, lo, hi, N)
+        assert ww == w1[i]
+        if ww == 0:
+            assert jj == c1[i] and np.float32(ss).view(np.uint32) == o1[i].view(np.uint32), i
