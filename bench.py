@@ -33,7 +33,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published peak
 B_ALG = {1: 32.0, 0: 48.0}     # algorithmic bytes per particle-step (FP32 state, FP64)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_particle_kernel_large_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_particle_kernel_large_traffic.txt")
 KERNEL_SOURCES = ["paper_2308_13092_amd/csrc/kernels_particles.hip",
                   "paper_2308_13092_amd/csrc/device.h"]
 

@@ -109,11 +109,17 @@ _lib = None
 
 
 def load(path=LIB_PATH):
-    """Load libecpic.so (raises if it has not been built)."""
+    """Load libecpic.so (raises if it has not been built).
+
+    torch is imported first: it brings its own HIP runtime, and the library
+    must bind to that same runtime (its soname is already loaded then), since
+    the device arena and the stream it is given come from torch.
+    """
     global _lib
     if _lib is None:
         if not os.path.exists(path):
             raise RuntimeError(f"{path} is missing: build it with python -m paper_2308_13092_amd.build")
+        import torch  # noqa: F401  (one HIP runtime per process: torch's)
         lib = C.CDLL(path)
         for name, res, args in SIGNATURES:
             fn = getattr(lib, name)
@@ -202,7 +208,8 @@ class Context:
         st = self.lib.pic_init(arr, len(cfgs), C.c_void_p(self.arena.data_ptr()), self.nbytes,
                                C.c_void_p(self.stream.cuda_stream), C.byref(self.ctx))
         if st != PIC_OK:
-            raise PicError(st, "pic_init failed")
+            msg = self.lib.pic_last_error(None)
+            raise PicError(st, "pic_init: " + (msg.decode() if msg else ""))
         self.n_inst = len(cfgs)
         self.prec = next((int(c.get("precision", 0)) for c in cfgs if c.get("n_cells", 0)), 0)
 

@@ -227,8 +227,13 @@ struct pic_ctx {
   std::vector<int64_t> ev_particles;
 };
 
+// Message of the last failure of a call that had no context to hold it
+// (pic_init); returned by pic_last_error(NULL).
+static thread_local std::string g_init_err;
+
 static pic_status fail(pic_ctx *c, pic_status s, const std::string &m) {
   if (c) c->err = m;
+  g_init_err = m;
   return s;
 }
 #define HIP_TRY(ctx, expr)                                                          \
@@ -270,7 +275,7 @@ static int particle_grid(const pic_ctx *c) {
   return c->n_cu * per;
 }
 static int sort_grid(const pic_ctx *c) { return c->n_cu * 4; }
-static int drain_grid(const pic_ctx *c) { return c->n_cu; }
+static int drain_grid(const pic_ctx *c) { return c->n_cu * 4; }
 
 // Fill InstDev for slot i from its config and block offset; write host arrays.
 static pic_status setup_slot(pic_ctx *c, int i, const pic_config &cfg) {
@@ -594,18 +599,22 @@ pic_status pic_init(const pic_config *cfgs, int32_t n_inst, void *device_arena, 
                     void *hip_stream, pic_ctx **out) {
   if (!out) return PIC_EINVAL;
   *out = nullptr;
-  if (!cfgs || n_inst <= 0 || n_inst > PIC_MAX_INSTANCES || !device_arena) return PIC_EINVAL;
+  if (!cfgs || n_inst <= 0 || n_inst > PIC_MAX_INSTANCES || !device_arena)
+    return fail(nullptr, PIC_EINVAL, "bad pic_init arguments");
   int prec = -1;
   for (int i = 0; i < n_inst; ++i) {
-    if (!validate(cfgs[i]).empty()) return PIC_EINVAL;
+    const std::string why = validate(cfgs[i]);
+    if (!why.empty()) return fail(nullptr, PIC_EINVAL, "config " + std::to_string(i) + ": " + why);
     if (cfgs[i].n_cells > 0) {
-      if (prec >= 0 && cfgs[i].precision != prec) return PIC_EINVAL;
+      if (prec >= 0 && cfgs[i].precision != prec)
+        return fail(nullptr, PIC_EINVAL, "all instances of a context share one precision");
       prec = cfgs[i].precision;
     }
   }
   if (prec < 0) prec = cfgs[0].precision == PIC_FP32_STATE ? 1 : 0;
   const size_t need = pic_footprint(cfgs, n_inst);
-  if (arena_bytes < need) return PIC_ENOMEM;
+  if (arena_bytes < need)
+    return fail(nullptr, PIC_ENOMEM, "arena smaller than pic_footprint: " + std::to_string(need));
 
   pic_ctx *c = new pic_ctx();
   c->stream = (hipStream_t)hip_stream;
@@ -667,6 +676,7 @@ pic_status pic_init(const pic_config *cfgs, int32_t n_inst, void *device_arena, 
     }
   }
   if (r != PIC_OK) {
+    g_init_err = c->err;
     pic_destroy(c);
     return r;
   }
@@ -684,7 +694,7 @@ void pic_destroy(pic_ctx *c) {
   delete c;
 }
 
-const char *pic_last_error(const pic_ctx *c) { return c ? c->err.c_str() : "null context"; }
+const char *pic_last_error(const pic_ctx *c) { return c ? c->err.c_str() : g_init_err.c_str(); }
 
 pic_status pic_deposit(pic_ctx *c) {
   if (!c) return PIC_EINVAL;
@@ -780,6 +790,11 @@ pic_status pic_diagnostics(pic_ctx *c, int32_t inst, pic_diag *out) {
   out->status = S.status;
   out->n_samples = S.n_samples;
   out->eedf_samples = S.eedf_samples;
+  auto ctr = [&](int i) {
+    unsigned long long v = 0;
+    for (int r = 0; r < kRep; ++r) v += S.ctr[i][r];
+    return v;
+  };
   for (int s = 0; s < 2; ++s) {
     out->n_live[s] = s < I.nsp ? (int64_t)w[D_LIVE0 + s] : 0;
     out->extent[s] = S.extent[s];
@@ -789,19 +804,19 @@ pic_status pic_diagnostics(pic_ctx *c, int32_t inst, pic_diag *out) {
     out->deposit_total[s] = s < I.nsp ? tot : 0;
     out->kinetic_j_m2[s] = I.W * kQE * ((double)w[D_KE0 + s] * 0x1p-20);
     for (int wl = 0; wl < 2; ++wl) {
-      out->absorbed[s][wl] = (int64_t)S.ctr[C_ABS + 2 * s + wl];
-      out->absorbed_energy_ev[s][wl] = (double)S.ctr[C_EABS + 2 * s + wl] / 65536.0;
+      out->absorbed[s][wl] = (int64_t)ctr(C_ABS + 2 * s + wl);
+      out->absorbed_energy_ev[s][wl] = (double)ctr(C_EABS + 2 * s + wl) / 65536.0;
     }
-    out->candidates[s] = (int64_t)S.ctr[C_CAND + s];
+    out->candidates[s] = (int64_t)ctr(C_CAND + s);
   }
   out->field_j_m2 = S.field_energy;
-  out->see_emitted = (int64_t)S.ctr[C_SEE];
-  out->ionisations = (int64_t)S.ctr[C_IZ];
-  out->excitations = (int64_t)S.ctr[C_EX];
-  out->elastic = (int64_t)S.ctr[C_EL];
-  out->charge_exchange = (int64_t)S.ctr[C_CX];
-  out->bound_violations = (int64_t)S.ctr[C_BOUND];
-  out->particle_steps = (int64_t)S.ctr[C_PSTEPS];
+  out->see_emitted = (int64_t)ctr(C_SEE);
+  out->ionisations = (int64_t)ctr(C_IZ);
+  out->excitations = (int64_t)ctr(C_EX);
+  out->elastic = (int64_t)ctr(C_EL);
+  out->charge_exchange = (int64_t)ctr(C_CX);
+  out->bound_violations = (int64_t)ctr(C_BOUND);
+  out->particle_steps = (int64_t)ctr(C_PSTEPS);
   out->ne_max_m3 = S.ne_max;
   out->wpe_dt_max = std::sqrt(S.ne_max * kQE * kQE / (kEPS0 * kME)) * I.dt;
   double vmax;

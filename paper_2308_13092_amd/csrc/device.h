@@ -35,6 +35,10 @@ constexpr int32_t kINT32_MAX = 2147483647;
 constexpr int kMaxInst = 512;
 constexpr int kMaxCells = 2048;
 constexpr int kNctr = 24;
+// Counters updated by many workgroups are replicated: workgroup b adds into
+// replica b % kRep, so no single address takes an atomic from every
+// workgroup (same-address device atomics serialise); readers sum replicas.
+constexpr int kRep = 32;
 
 // Philox counter tags (counter word 1 = tag | species << 8).
 enum : uint32_t {
@@ -89,10 +93,10 @@ struct InstState {
   int32_t frozen, pad0;
   int64_t extent[2];
   unsigned long long append[2];
-  unsigned long long step_live[2];
-  unsigned long long step_absorbed[2];
+  unsigned long long step_live[2][kRep];
+  unsigned long long step_absorbed[2][kRep];
   int64_t n_live[2];
-  unsigned long long ctr[kNctr];
+  unsigned long long ctr[kNctr][kRep];
   double field_energy, ne_max;
   int32_t n_samples, eedf_samples;
   int64_t sort_live[2];
@@ -130,6 +134,48 @@ __host__ __device__ inline P64 view64(char *b, int64_t cap) {
   return p;
 }
 constexpr int64_t kBytes32 = 32, kBytes64 = 44;
+
+// Global-address-space access.  The particle arrays are reached through
+// pointers stored in the instance table, where the compiler no longer knows
+// they are global memory and would emit FLAT instructions; FLAT operations
+// also count against the LDS wait counter, so every LDS access after a store
+// would wait for that store to reach memory.
+#define ECPIC_GLOBAL __attribute__((address_space(1)))
+typedef int ecpic_iv4 __attribute__((ext_vector_type(4)));
+typedef float ecpic_fv4 __attribute__((ext_vector_type(4)));
+typedef double ecpic_dv2 __attribute__((ext_vector_type(2)));
+template <class V, class T>
+__device__ __forceinline__ V gload(const T *p) {
+  return *(const ECPIC_GLOBAL V *)p;
+}
+template <class V, class T>
+__device__ __forceinline__ void gstore(T *p, V v) {
+  *(ECPIC_GLOBAL V *)p = v;
+}
+__device__ __forceinline__ int4 gload4(const int *p) {
+  const ecpic_iv4 v = *(const ECPIC_GLOBAL ecpic_iv4 *)p;
+  return make_int4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ float4 gload4(const float *p) {
+  const ecpic_fv4 v = *(const ECPIC_GLOBAL ecpic_fv4 *)p;
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ double2 gload2(const double *p) {
+  const ecpic_dv2 v = *(const ECPIC_GLOBAL ecpic_dv2 *)p;
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void gstore4(int *p, int a, int b, int c, int d) {
+  ecpic_iv4 v = {a, b, c, d};
+  *(ECPIC_GLOBAL ecpic_iv4 *)p = v;
+}
+__device__ __forceinline__ void gstore4(float *p, float a, float b, float c, float d) {
+  ecpic_fv4 v = {a, b, c, d};
+  *(ECPIC_GLOBAL ecpic_fv4 *)p = v;
+}
+__device__ __forceinline__ void gstore2(double *p, double a, double b) {
+  ecpic_dv2 v = {a, b};
+  *(ECPIC_GLOBAL ecpic_dv2 *)p = v;
+}
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11) and the uniform / normal variates.

@@ -284,53 +284,31 @@ __device__ bool collide_ion(const InstDev &I, uint64_t id, int64_t k, double &vx
 struct Smem {
   int seg_prefix[2 * kMaxInst + 1];
   unsigned long long ctr[kNctr];
-  int is_last;
 };
 
-template <int BLOCK>
+// Sum over the 64 lanes of a wavefront (every lane gets the total).
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
 
-// Deposit of one record per lane (key = cell j, a0 -> node j, a1 -> node j+1)
-// into the LDS grid.  Runs of equal keys across the wavefront are summed and
-// added by their first lane; up to 4 rounds, then the rest go directly.
-__device__ __forceinline__ void deposit_wave(int64_t *sA, bool has, int key, unsigned long long a0,
-                                             unsigned long long a1) {
-  const int lane = __lane_id();
-  unsigned long long pending = __ballot(has);
-  int rounds = 0;
-  while (pending && rounds < 4) {
-    const int leader = __ffsll((long long)pending) - 1;
-    const int lkey = __shfl(key, leader, 64);
-    const bool match = has && key == lkey;
-    const unsigned long long mm = __ballot(match);
-    const unsigned long long s0 = wave_sum_u64<64>(match ? a0 : 0ull);
-    const unsigned long long s1 = wave_sum_u64<64>(match ? a1 : 0ull);
-    if (lane == leader) {
-      atomicAdd(reinterpret_cast<unsigned long long *>(&sA[lkey]), s0);
-      atomicAdd(reinterpret_cast<unsigned long long *>(&sA[lkey + 1]), s1);
-    }
-    if (match) has = false;
-    pending &= ~mm;
-    ++rounds;
-    if (__popcll(mm) < 4) break;   // scattered keys: stop merging
-  }
-  if (has) {
-    atomicAdd(reinterpret_cast<unsigned long long *>(&sA[key]), a0);
-    atomicAdd(reinterpret_cast<unsigned long long *>(&sA[key + 1]), a1);
-  }
-}
-
-// Per-thread accumulation of up to kPPT deposits: the run of the first valid
-// cell stays in registers for the wavefront merge, other cells go to LDS.
+// Per-thread accumulation of up to kPPT deposits: consecutive particles of a
+// thread in one cell (the usual case after a cell sort) are summed in
+// registers and added to LDS once; a different cell goes to LDS at once.
+// LDS 64-bit atomics on scattered addresses cost less than a cross-lane merge.
 struct DepAcc {
   bool has;
   int key;
   unsigned long long a0, a1;
   __device__ void init() { has = false; key = 0; a0 = 0; a1 = 0; }
+  // Add the held run to the workgroup's LDS accumulator.
+  __device__ void flush(int64_t *sA) {
+    if (has) {
+      atomicAdd(reinterpret_cast<unsigned long long *>(&sA[key]), a0);
+      atomicAdd(reinterpret_cast<unsigned long long *>(&sA[key + 1]), a1);
+    }
+  }
   __device__ void add(int64_t *sA, int j, int64_t w0, int64_t w1) {
     if (!has) { has = true; key = j; a0 = (unsigned long long)w0; a1 = (unsigned long long)w1; }
     else if (j == key) { a0 += (unsigned long long)w0; a1 += (unsigned long long)w1; }
@@ -363,9 +341,17 @@ __device__ __forceinline__ void eedf_sample(const InstDev &I, double x, double v
 }
 
 // Reserve a slot for a new particle of species s; -1 when the segment is full.
+// All lanes of the wavefront that call this together (same instance and
+// species) share one atomic: the first takes the whole group's slots.
 __device__ __forceinline__ int64_t append_slot(const InstDev &I, InstState &S, int s) {
-  const unsigned long long a = atomicAdd(&S.append[s], 1ull);
-  const int64_t idx = S.extent[s] + (int64_t)a;
+  const unsigned long long active = __ballot(true);
+  const int lane = __lane_id();
+  const int leader = __ffsll((long long)active) - 1;
+  const int rank = __popcll(active & ((1ull << lane) - 1ull));
+  unsigned long long base = 0;
+  if (lane == leader) base = atomicAdd(&S.append[s], (unsigned long long)__popcll(active));
+  base = __shfl(base, leader, 64);
+  const int64_t idx = S.extent[s] + (int64_t)(base + (unsigned long long)rank);
   if (idx >= I.cap[s]) {
     set_status(S, ST_CAPACITY);
     return -1;
@@ -497,18 +483,13 @@ template <int BLOCK>
 __device__ void flush_counters(Smem &sm, InstState *Sp, int sp) {
   __syncthreads();
   const int t = threadIdx.x;
+  const int r = blockIdx.x & (kRep - 1);
   if (t < kNctr) {
     const unsigned long long v = sm.ctr[t];
     if (v) {
-      if (t == C_PSTEPS) {
-        atomicAdd(&Sp->ctr[C_PSTEPS], v);
-        atomicAdd(&Sp->step_live[sp], v);
-      } else if (t >= C_ABS && t < C_ABS + 4) {
-        atomicAdd(&Sp->ctr[t], v);
-        atomicAdd(&Sp->step_absorbed[(t - C_ABS) >> 1], v);
-      } else {
-        atomicAdd(&Sp->ctr[t], v);
-      }
+      atomicAdd(&Sp->ctr[t][r], v);
+      if (t == C_PSTEPS) atomicAdd(&Sp->step_live[sp][r], v);
+      else if (t >= C_ABS && t < C_ABS + 4) atomicAdd(&Sp->step_absorbed[(t - C_ABS) >> 1][r], v);
       sm.ctr[t] = 0;
     }
   }
@@ -572,7 +553,7 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
       unsigned long long b = 0;
       if (lane == 0) b = atomicAdd(&Sp->qcount[sp], (unsigned long long)n);
       b = __shfl(b, 0, 64);
-      if (lane < n) gq[b + lane] = wq[wq_n - n + lane];
+      if (lane < n) gstore<int>(gq + b + lane, wq[wq_n - n + lane]);
       wq_n -= n;
     }
   };
@@ -594,7 +575,7 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
         }
       }
     }
-    const unsigned long long lw = wave_sum_u64<64>(live_here);
+    const unsigned long long lw = wave_sum_u64(live_here);
     if (lane == 0 && lw) atomicAdd(&sm.ctr[C_PSTEPS], lw);
     live_here = 0;
     flush_counters<BLOCK>(sm, Sp, sp);
@@ -659,18 +640,18 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
       int c[kPPT], kn[kPPT];
       float o[kPPT], vx[kPPT];
       if (full) {
-        const int4 c4 = *reinterpret_cast<const int4 *>(P.cell + i0);
+        const int4 c4 = gload4(P.cell + i0);
         c[0] = c4.x; c[1] = c4.y; c[2] = c4.z; c[3] = c4.w;
         if (MODE != M_MCC) {
-          const float4 o4 = *reinterpret_cast<const float4 *>(P.off + i0);
+          const float4 o4 = gload4(P.off + i0);
           o[0] = o4.x; o[1] = o4.y; o[2] = o4.z; o[3] = o4.w;
         }
         if (MODE != M_DEPOSIT && MODE != M_MCC) {
-          const float4 v4 = *reinterpret_cast<const float4 *>(P.vx + i0);
+          const float4 v4 = gload4(P.vx + i0);
           vx[0] = v4.x; vx[1] = v4.y; vx[2] = v4.z; vx[3] = v4.w;
         }
         if (MODE == M_MCC || MODE == M_FUSED) {
-          const int4 k4 = *reinterpret_cast<const int4 *>(P.knext + i0);
+          const int4 k4 = gload4(P.knext + i0);
           kn[0] = k4.x; kn[1] = k4.y; kn[2] = k4.z; kn[3] = k4.w;
         }
       } else {
@@ -678,10 +659,10 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
         for (int q = 0; q < kPPT; ++q) {
           const int64_t i = i0 + q;
           const bool v = i < ext;
-          c[q] = v ? P.cell[i] : -1;
-          o[q] = v ? P.off[i] : 0.0f;
-          vx[q] = v ? P.vx[i] : 0.0f;
-          kn[q] = v ? P.knext[i] : 0;
+          c[q] = v ? gload<int>(P.cell + i) : -1;
+          o[q] = v ? gload<float>(P.off + i) : 0.0f;
+          vx[q] = v ? gload<float>(P.vx + i) : 0.0f;
+          kn[q] = v ? gload<int>(P.knext + i) : 0;
         }
       }
       int cn[kPPT];
@@ -742,24 +723,24 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
           }
         }
       }
-      if constexpr (MODE == M_DEPOSIT || MODE == M_FUSED) deposit_wave(sA, dep.has, dep.key, dep.a0, dep.a1);
+      if constexpr (MODE == M_DEPOSIT || MODE == M_FUSED) dep.flush(sA);
       if constexpr (MODE == M_PUSH || MODE == M_FUSED || MODE == M_PULLBACK) {
         if (full) {
           if constexpr (MODE != M_PULLBACK) {
-            *reinterpret_cast<int4 *>(P.cell + i0) = make_int4(cn[0], cn[1], cn[2], cn[3]);
-            *reinterpret_cast<float4 *>(P.off + i0) = make_float4(on[0], on[1], on[2], on[3]);
+            gstore4(P.cell + i0, cn[0], cn[1], cn[2], cn[3]);
+            gstore4(P.off + i0, on[0], on[1], on[2], on[3]);
           }
-          *reinterpret_cast<float4 *>(P.vx + i0) = make_float4(vn[0], vn[1], vn[2], vn[3]);
+          gstore4(P.vx + i0, vn[0], vn[1], vn[2], vn[3]);
         } else {
 #pragma unroll
           for (int q = 0; q < kPPT; ++q) {
             const int64_t i = i0 + q;
             if (i < ext) {
               if constexpr (MODE != M_PULLBACK) {
-                P.cell[i] = cn[q];
-                P.off[i] = on[q];
+                gstore<int>(P.cell + i, cn[q]);
+                gstore<float>(P.off + i, on[q]);
               }
-              P.vx[i] = vn[q];
+              gstore<float>(P.vx + i, vn[q]);
             }
           }
         }
@@ -769,16 +750,16 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
       double x[kPPT], vx[kPPT];
       int kn[kPPT];
       if (full) {
-        const double2 xa = *reinterpret_cast<const double2 *>(P.x + i0);
-        const double2 xb = *reinterpret_cast<const double2 *>(P.x + i0 + 2);
+        const double2 xa = gload2(P.x + i0);
+        const double2 xb = gload2(P.x + i0 + 2);
         x[0] = xa.x; x[1] = xa.y; x[2] = xb.x; x[3] = xb.y;
         if (MODE != M_DEPOSIT && MODE != M_MCC) {
-          const double2 va = *reinterpret_cast<const double2 *>(P.vx + i0);
-          const double2 vb = *reinterpret_cast<const double2 *>(P.vx + i0 + 2);
+          const double2 va = gload2(P.vx + i0);
+          const double2 vb = gload2(P.vx + i0 + 2);
           vx[0] = va.x; vx[1] = va.y; vx[2] = vb.x; vx[3] = vb.y;
         }
         if (MODE == M_MCC || MODE == M_FUSED) {
-          const int4 k4 = *reinterpret_cast<const int4 *>(P.knext + i0);
+          const int4 k4 = gload4(P.knext + i0);
           kn[0] = k4.x; kn[1] = k4.y; kn[2] = k4.z; kn[3] = k4.w;
         }
       } else {
@@ -786,9 +767,9 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
         for (int q = 0; q < kPPT; ++q) {
           const int64_t i = i0 + q;
           const bool v = i < ext;
-          x[q] = v ? P.x[i] : -1.0;
-          vx[q] = v ? P.vx[i] : 0.0;
-          kn[q] = v ? P.knext[i] : 0;
+          x[q] = v ? gload<double>(P.x + i) : -1.0;
+          vx[q] = v ? gload<double>(P.vx + i) : 0.0;
+          kn[q] = v ? gload<int>(P.knext + i) : 0;
         }
       }
       double xn[kPPT], vn[kPPT];
@@ -854,22 +835,22 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
           }
         }
       }
-      if constexpr (MODE == M_DEPOSIT || MODE == M_FUSED) deposit_wave(sA, dep.has, dep.key, dep.a0, dep.a1);
+      if constexpr (MODE == M_DEPOSIT || MODE == M_FUSED) dep.flush(sA);
       if constexpr (MODE == M_PUSH || MODE == M_FUSED || MODE == M_PULLBACK) {
         if (full) {
           if constexpr (MODE != M_PULLBACK) {
-            *reinterpret_cast<double2 *>(P.x + i0) = make_double2(xn[0], xn[1]);
-            *reinterpret_cast<double2 *>(P.x + i0 + 2) = make_double2(xn[2], xn[3]);
+            gstore2(P.x + i0, xn[0], xn[1]);
+            gstore2(P.x + i0 + 2, xn[2], xn[3]);
           }
-          *reinterpret_cast<double2 *>(P.vx + i0) = make_double2(vn[0], vn[1]);
-          *reinterpret_cast<double2 *>(P.vx + i0 + 2) = make_double2(vn[2], vn[3]);
+          gstore2(P.vx + i0, vn[0], vn[1]);
+          gstore2(P.vx + i0 + 2, vn[2], vn[3]);
         } else {
 #pragma unroll
           for (int q = 0; q < kPPT; ++q) {
             const int64_t i = i0 + q;
             if (i < ext) {
-              if constexpr (MODE != M_PULLBACK) P.x[i] = xn[q];
-              P.vx[i] = vn[q];
+              if constexpr (MODE != M_PULLBACK) gstore<double>(P.x + i, xn[q]);
+              gstore<double>(P.vx + i, vn[q]);
             }
           }
         }
@@ -1006,42 +987,43 @@ k_drain(const InstDev *__restrict__ insts, InstState *__restrict__ states, int n
     }
   }
   if (seg >= 0) flush_counters<BLOCK>(sm, Sp, seg & 1);
+}
 
-  __threadfence();
-  __syncthreads();
-  if (t == 0) sm.is_last = (atomicAdd(done, 1u) == gridDim.x - 1);
-  __syncthreads();
-  if (sm.is_last) {
-    __threadfence();
-    for (int i = t; i < n_inst; i += BLOCK) {
-      const InstDev &I = insts[i];
-      InstState &S = states[i];
-      if (!I.active || S.frozen != 0 || (I.k_stop > 0 && S.k >= I.k_stop)) continue;
-      for (int s = 0; s < I.nsp; ++s) {
-        S.qcount[s] = 0;
-        if constexpr (MODE == M_MCC || MODE == M_FUSED) {
-          const unsigned long long app = atomicAdd(&S.append[s], 0ull);
-          const unsigned long long lv = atomicAdd(&S.step_live[s], 0ull);
-          const unsigned long long ab = atomicAdd(&S.step_absorbed[s], 0ull);
-          int64_t add = (int64_t)app;
-          if (S.extent[s] + add > I.cap[s]) add = I.cap[s] - S.extent[s];
-          S.extent[s] += add;
-          const int64_t live = (MODE == M_FUSED) ? ((int64_t)lv - (int64_t)ab + add)
-                                                 : (S.n_live[s] - (int64_t)ab + add);
-          S.n_live[s] = live;
-          if ((double)live > I.growth_limit * (double)I.n_init[s] && I.n_init[s] > 0)
-            atomicOr(&S.status, (int)ST_GROWTH);
-          S.append[s] = 0;
-          S.step_live[s] = 0;
-          S.step_absorbed[s] = 0;
+// Close a pass: clear the queues; in the modes that end a step, new
+// particles join the extents, the live count is updated and checked against
+// the growth limit, and k advances.  One workgroup, one thread per instance.
+template <int MODE>
+__global__ void __launch_bounds__(256)
+k_finalize(const InstDev *__restrict__ insts, InstState *__restrict__ states, int n_inst) {
+  for (int i = threadIdx.x; i < n_inst; i += blockDim.x) {
+    const InstDev &I = insts[i];
+    InstState &S = states[i];
+    if (!I.active || S.frozen != 0 || (I.k_stop > 0 && S.k >= I.k_stop)) continue;
+    for (int s = 0; s < I.nsp; ++s) {
+      S.qcount[s] = 0;
+      if (MODE == M_MCC || MODE == M_FUSED) {
+        unsigned long long lv = 0, ab = 0;
+        for (int r = 0; r < kRep; ++r) {
+          lv += S.step_live[s][r];
+          ab += S.step_absorbed[s][r];
+          S.step_live[s][r] = 0;
+          S.step_absorbed[s][r] = 0;
         }
-      }
-      if constexpr (MODE == M_MCC || MODE == M_FUSED) {
-        S.k += 1;
-        if (atomicOr(&S.status, 0) != 0) S.frozen = 1;
+        int64_t add = (int64_t)S.append[s];
+        if (S.extent[s] + add > I.cap[s]) add = I.cap[s] - S.extent[s];
+        S.extent[s] += add;
+        const int64_t live = (MODE == M_FUSED) ? ((int64_t)lv - (int64_t)ab + add)
+                                               : (S.n_live[s] - (int64_t)ab + add);
+        S.n_live[s] = live;
+        if ((double)live > I.growth_limit * (double)I.n_init[s] && I.n_init[s] > 0)
+          S.status |= ST_GROWTH;
+        S.append[s] = 0;
       }
     }
-    if (t == 0) *done = 0u;
+    if (MODE == M_MCC || MODE == M_FUSED) {
+      S.k += 1;
+      if (S.status != 0) S.frozen = 1;
+    }
   }
 }
 
@@ -1107,8 +1089,8 @@ k_diag(const InstDev *__restrict__ insts, const InstState *__restrict__ states, 
       ke += (unsigned long long)rint(en * 1048576.0);
       vmax = fmax(vmax, fabs(vx));
     }
-    live = wave_sum_u64<64>(live);
-    ke = wave_sum_u64<64>(ke);
+    live = wave_sum_u64(live);
+    ke = wave_sum_u64(ke);
     for (int o = 32; o > 0; o >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, o, 64));
     if (__lane_id() == 0) {
       atomicAdd(&out[D_LIVE0 + s], live);
@@ -1155,12 +1137,15 @@ static hipError_t launch_drain_form(const InstDev *insts, InstState *states, int
   switch (mode) {
     case M_PUSH:
       hipLaunchKernelGGL((k_drain<F, M_PUSH>), dim3(grid), dim3(256), 0, s, insts, states, n_inst, done);
+      hipLaunchKernelGGL((k_finalize<M_PUSH>), dim3(1), dim3(256), 0, s, insts, states, n_inst);
       break;
     case M_MCC:
       hipLaunchKernelGGL((k_drain<F, M_MCC>), dim3(grid), dim3(256), 0, s, insts, states, n_inst, done);
+      hipLaunchKernelGGL((k_finalize<M_MCC>), dim3(1), dim3(256), 0, s, insts, states, n_inst);
       break;
     case M_FUSED:
       hipLaunchKernelGGL((k_drain<F, M_FUSED>), dim3(grid), dim3(256), 0, s, insts, states, n_inst, done);
+      hipLaunchKernelGGL((k_finalize<M_FUSED>), dim3(1), dim3(256), 0, s, insts, states, n_inst);
       break;
     default:
       return hipErrorInvalidValue;

@@ -8,9 +8,9 @@
 //   count   per-workgroup LDS histogram of the live cells, added to HBM;
 //   scan    one workgroup per instance: exclusive prefix of the counts gives
 //           each cell's first destination slot;
-//   scatter ranks within a wavefront from ballots, one reservation per
+//   scatter ranks within the tile from LDS atomics, one reservation per
 //           (tile, cell) with an HBM atomic, then every field is copied to its
-//           destination.  The last workgroup flips the buffers.
+//           destination; a one-workgroup kernel then flips the buffers.
 // Order within a cell is not defined; results depend on the particle set only.
 #include "device.h"
 #include "kernels.h"
@@ -23,7 +23,6 @@ constexpr int kSTile = kSB * kSPPT;
 
 struct SortSmem {
   int seg_prefix[2 * kMaxInst + 1];
-  int is_last;
 };
 
 __device__ __forceinline__ int key_of(const InstDev &I, const P32 &P, int64_t i, const double *,
@@ -166,26 +165,114 @@ k_sort_scan(const InstDev *__restrict__ insts, InstState *__restrict__ states) {
   }
 }
 
-template <class P>
-__device__ __forceinline__ void copy_particle(const P &src, int64_t i, const P &dst, int64_t d);
-template <>
-__device__ __forceinline__ void copy_particle<P32>(const P32 &src, int64_t i, const P32 &dst, int64_t d) {
-  dst.cell[d] = src.cell[i];
-  dst.off[d] = src.off[i];
-  dst.vx[d] = src.vx[i];
-  dst.vy[d] = src.vy[i];
-  dst.vz[d] = src.vz[i];
-  dst.knext[d] = src.knext[i];
-  dst.id[d] = src.id[i];
+// One particle's fields in registers.
+struct Rec32 {
+  int cell; float off, vx, vy, vz; int knext; uint64_t id;
+};
+struct Rec64 {
+  double x, vx, vy, vz; int knext; uint64_t id;
+};
+template <class P> struct RecOf;
+template <> struct RecOf<P32> { using T = Rec32; };
+template <> struct RecOf<P64> { using T = Rec64; };
+
+// Load the 4 consecutive particles of a thread (vector loads when all four
+// are inside the extent).
+__device__ __forceinline__ void load_recs(const P32 &P, int64_t i0, int64_t ext, Rec32 *r, bool *ok) {
+  if (i0 + 4 <= ext) {
+    const int4 c = gload4(P.cell + i0);
+    const float4 o = gload4(P.off + i0), x = gload4(P.vx + i0), y = gload4(P.vy + i0),
+                 z = gload4(P.vz + i0);
+    const int4 k = gload4(P.knext + i0);
+    const ecpic_iv4 ia = *(const ECPIC_GLOBAL ecpic_iv4 *)(P.id + i0);
+    const ecpic_iv4 ib = *(const ECPIC_GLOBAL ecpic_iv4 *)(P.id + i0 + 2);
+    const int cc[4] = {c.x, c.y, c.z, c.w};
+    const float oo[4] = {o.x, o.y, o.z, o.w}, xx[4] = {x.x, x.y, x.z, x.w},
+                yy[4] = {y.x, y.y, y.z, y.w}, zz[4] = {z.x, z.y, z.z, z.w};
+    const int kk[4] = {k.x, k.y, k.z, k.w};
+    const uint64_t ii[4] = {(uint64_t)(uint32_t)ia.x | ((uint64_t)(uint32_t)ia.y << 32),
+                            (uint64_t)(uint32_t)ia.z | ((uint64_t)(uint32_t)ia.w << 32),
+                            (uint64_t)(uint32_t)ib.x | ((uint64_t)(uint32_t)ib.y << 32),
+                            (uint64_t)(uint32_t)ib.z | ((uint64_t)(uint32_t)ib.w << 32)};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      r[q] = Rec32{cc[q], oo[q], xx[q], yy[q], zz[q], kk[q], ii[q]};
+      ok[q] = true;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t i = i0 + q;
+      ok[q] = i < ext;
+      if (ok[q])
+        r[q] = Rec32{P.cell[i], P.off[i], P.vx[i], P.vy[i], P.vz[i], P.knext[i], P.id[i]};
+    }
+  }
 }
-template <>
-__device__ __forceinline__ void copy_particle<P64>(const P64 &src, int64_t i, const P64 &dst, int64_t d) {
-  dst.x[d] = src.x[i];
-  dst.vx[d] = src.vx[i];
-  dst.vy[d] = src.vy[i];
-  dst.vz[d] = src.vz[i];
-  dst.knext[d] = src.knext[i];
-  dst.id[d] = src.id[i];
+__device__ __forceinline__ void load_recs(const P64 &P, int64_t i0, int64_t ext, Rec64 *r, bool *ok) {
+  if (i0 + 4 <= ext) {
+    const double2 xa = gload2(P.x + i0), xb = gload2(P.x + i0 + 2);
+    const double2 ua = gload2(P.vx + i0), ub = gload2(P.vx + i0 + 2);
+    const double2 va = gload2(P.vy + i0), vb = gload2(P.vy + i0 + 2);
+    const double2 wa = gload2(P.vz + i0), wb = gload2(P.vz + i0 + 2);
+    const int4 k = gload4(P.knext + i0);
+    const ecpic_iv4 ia = *(const ECPIC_GLOBAL ecpic_iv4 *)(P.id + i0);
+    const ecpic_iv4 ib = *(const ECPIC_GLOBAL ecpic_iv4 *)(P.id + i0 + 2);
+    const double xx[4] = {xa.x, xa.y, xb.x, xb.y}, uu[4] = {ua.x, ua.y, ub.x, ub.y},
+                 vv[4] = {va.x, va.y, vb.x, vb.y}, ww[4] = {wa.x, wa.y, wb.x, wb.y};
+    const int kk[4] = {k.x, k.y, k.z, k.w};
+    const uint64_t ii[4] = {(uint64_t)(uint32_t)ia.x | ((uint64_t)(uint32_t)ia.y << 32),
+                            (uint64_t)(uint32_t)ia.z | ((uint64_t)(uint32_t)ia.w << 32),
+                            (uint64_t)(uint32_t)ib.x | ((uint64_t)(uint32_t)ib.y << 32),
+                            (uint64_t)(uint32_t)ib.z | ((uint64_t)(uint32_t)ib.w << 32)};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      r[q] = Rec64{xx[q], uu[q], vv[q], ww[q], kk[q], ii[q]};
+      ok[q] = true;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t i = i0 + q;
+      ok[q] = i < ext;
+      if (ok[q]) r[q] = Rec64{P.x[i], P.vx[i], P.vy[i], P.vz[i], P.knext[i], P.id[i]};
+    }
+  }
+}
+__device__ __forceinline__ void store_rec(const P32 &P, int64_t d, const Rec32 &r) {
+  gstore<int>(P.cell + d, r.cell);
+  gstore<float>(P.off + d, r.off);
+  gstore<float>(P.vx + d, r.vx);
+  gstore<float>(P.vy + d, r.vy);
+  gstore<float>(P.vz + d, r.vz);
+  gstore<int>(P.knext + d, r.knext);
+  gstore<uint64_t>(P.id + d, r.id);
+}
+__device__ __forceinline__ void store_rec(const P64 &P, int64_t d, const Rec64 &r) {
+  gstore<double>(P.x + d, r.x);
+  gstore<double>(P.vx + d, r.vx);
+  gstore<double>(P.vy + d, r.vy);
+  gstore<double>(P.vz + d, r.vz);
+  gstore<int>(P.knext + d, r.knext);
+  gstore<uint64_t>(P.id + d, r.id);
+}
+__device__ __forceinline__ int rec_key(const InstDev &I, const Rec32 &r, const double *) {
+  return (r.cell >= 0 && r.cell < I.N) ? r.cell : -1;
+}
+__device__ __forceinline__ int rec_key(const InstDev &I, const Rec64 &r, const double *nodes) {
+  const double x = r.x;
+  if (!(x >= 0.0 && x < I.L)) return -1;
+  if (I.uniform) {
+    const int j = (int)floor(x / I.dx);
+    return j >= I.N ? I.N - 1 : j;
+  }
+  int lo = 0, hi = I.N;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (nodes[mid] <= x) lo = mid;
+    else hi = mid;
+  }
+  return lo;
 }
 
 template <class P>
@@ -203,8 +290,6 @@ k_sort_scatter(const InstDev *__restrict__ insts, InstState *__restrict__ states
   const int nseg = 2 * n_inst;
   const int64_t T = sm.seg_prefix[nseg];
   const int64_t t0 = T * blockIdx.x / gridDim.x, t1 = T * (blockIdx.x + 1) / gridDim.x;
-  const int lane = __lane_id();
-  const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   int seg = -1;
   const InstDev *Ip = nullptr;
   P src, dst;
@@ -227,30 +312,17 @@ k_sort_scatter(const InstDev *__restrict__ insts, InstState *__restrict__ states
     }
     const InstDev &I = *Ip;
     const int64_t i0 = (tile - sm.seg_prefix[seg]) * kSTile + (int64_t)threadIdx.x * kSPPT;
+    typename RecOf<P>::T r[kSPPT];
+    bool ok[kSPPT];
+    load_recs(src, i0, ext, r, ok);
     int key[kSPPT];
     unsigned int rank[kSPPT];
+    // Rank of each particle among the tile's particles of its cell (LDS
+    // atomics; the order within a cell is not defined).
 #pragma unroll
     for (int q = 0; q < kSPPT; ++q) {
-      const int64_t i = i0 + q;
-      key[q] = (i < ext) ? key_of(I, src, i, sNodes, nullptr) : -1;
-      rank[q] = 0;
-      // Ranks of equal keys within the wavefront, one LDS atomic per run.
-      bool pending = key[q] >= 0;
-      unsigned long long pm = __ballot(pending);
-      while (pm) {
-        const int leader = __ffsll((long long)pm) - 1;
-        const int lkey = __shfl(key[q], leader, 64);
-        const bool match = pending && key[q] == lkey;
-        const unsigned long long mm = __ballot(match);
-        unsigned int b = 0;
-        if (lane == leader) b = atomicAdd(&cnt[lkey], (unsigned int)__popcll(mm));
-        b = __shfl(b, leader, 64);
-        if (match) {
-          rank[q] = b + (unsigned int)__popcll(mm & lt_mask);
-          pending = false;
-        }
-        pm &= ~mm;
-      }
+      key[q] = ok[q] ? rec_key(I, r[q], sNodes) : -1;
+      rank[q] = (key[q] >= 0) ? atomicAdd(&cnt[key[q]], 1u) : 0u;
     }
     __syncthreads();
     // The first particle of each cell in the tile reserves the tile's range.
@@ -261,30 +333,26 @@ k_sort_scatter(const InstDev *__restrict__ insts, InstState *__restrict__ states
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < kSPPT; ++q)
-      if (key[q] >= 0) copy_particle<P>(src, i0 + q, dst, (int64_t)(gbase[key[q]] + rank[q]));
+      if (key[q] >= 0) store_rec(dst, (int64_t)(gbase[key[q]] + rank[q]), r[q]);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < kSPPT; ++q)
       if (key[q] >= 0 && rank[q] == 0) cnt[key[q]] = 0;
   }
-  // The last workgroup switches every sorted instance to the new buffer.
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) sm.is_last = (atomicAdd(done, 1u) == gridDim.x - 1);
-  __syncthreads();
-  if (sm.is_last) {
-    __threadfence();
-    for (int i = threadIdx.x; i < n_inst; i += kSB) {
-      const InstDev &I = insts[i];
-      InstState &S = states[i];
-      if (!I.active || S.frozen != 0) continue;
-      for (int s = 0; s < I.nsp; ++s) {
-        S.extent[s] = S.sort_live[s];
-        S.n_live[s] = S.sort_live[s];
-      }
-      S.parity ^= 1;
+}
+
+// Switch every sorted instance to the new buffer.
+__global__ void __launch_bounds__(256)
+k_sort_finish(const InstDev *__restrict__ insts, InstState *__restrict__ states, int n_inst) {
+  for (int i = threadIdx.x; i < n_inst; i += blockDim.x) {
+    const InstDev &I = insts[i];
+    InstState &S = states[i];
+    if (!I.active || S.frozen != 0) continue;
+    for (int s = 0; s < I.nsp; ++s) {
+      S.extent[s] = S.sort_live[s];
+      S.n_live[s] = S.sort_live[s];
     }
-    if (threadIdx.x == 0) *done = 0u;
+    S.parity ^= 1;
   }
 }
 
@@ -304,6 +372,7 @@ hipError_t launch_sort(const InstDev *insts, InstState *states, int n_inst, int 
     hipLaunchKernelGGL(k_sort_scatter<P32>, dim3(grid), dim3(kSB), lds, s, insts, states, n_inst, max_n, done);
   else
     hipLaunchKernelGGL(k_sort_scatter<P64>, dim3(grid), dim3(kSB), lds, s, insts, states, n_inst, max_n, done);
+  hipLaunchKernelGGL(k_sort_finish, dim3(1), dim3(256), 0, s, insts, states, n_inst);
   return hipGetLastError();
 }
 

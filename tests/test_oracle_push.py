@@ -239,3 +239,50 @@ def test_run_collapsed_walk_equals_cell_walk_bitwise():
         assert ww == w1[i]
         if ww == 0:
             assert jj == c1[i] and np.float32(ss).view(np.uint32) == o1[i].view(np.uint32), i
+
+
+def test_in_run_single_step_equals_cell_walk_bitwise():
+    """A move that stays inside the run of equal cells around the start cell is
+    sigma - floor(sigma) in one FP32 operation (with a carry when a left move
+    rounds up to 1); the GPU kernel takes this shortcut before walking."""
+    from oracle.grid import refined_nodes
+    L = 0.03
+    nodes = refined_nodes(L, L / 1024, L / 128, 0.004)
+    N = len(nodes) - 1
+    g = Grid.make(L, N, nodes)
+    _, rf, rb = g.walk_tables(1e-10)
+    lo = np.zeros(N, int)
+    hi = np.zeros(N, int)
+    j = 0
+    while j < N:
+        e = j
+        while e + 1 < N and rf[e] == 1.0 and rb[e] == 1.0:
+            e += 1
+        lo[j:e + 1] = j
+        hi[j:e + 1] = e
+        j = e + 1
+    r = inputs.rng(26)
+    n = 30000
+    cell = r.integers(0, N, n).astype(np.int32)
+    sig = np.concatenate([r.uniform(-40, 40, n - 3000), -(10.0 ** r.uniform(-12, 0, 2000)),
+                          r.uniform(-1.0, 2.0, 1000)]).astype(np.float32)
+    sp = Species(s=0, prec=FP32, vx=np.zeros(n, np.float32), vy=np.zeros(n, np.float32),
+                 vz=np.zeros(n, np.float32), id=np.arange(n, dtype=np.uint64),
+                 knext=np.zeros(n, np.int64), cell=cell, off=sig)
+    zero = np.zeros(N, np.float32)
+    _, c1, o1, w1 = push_fp32(g, sp, zero, 0, np.float32(0.0), (zero, rf, rb))
+    used = 0
+    for i in range(n):
+        s = np.float32(sig[i])
+        j0 = int(cell[i])
+        if s < 0 or s >= 1:
+            m = np.float32(np.floor(s))
+            jm = j0 + int(m)
+            if lo[j0] <= jm <= hi[j0]:
+                s2 = np.float32(s - m)
+                if s2 >= np.float32(1.0):
+                    s2 = np.float32(0.0)
+                    jm += 1
+                used += 1
+                assert w1[i] == 0 and c1[i] == jm and s2.view(np.uint32) == o1[i].view(np.uint32), i
+    assert used > n // 2
