@@ -65,7 +65,10 @@ def run_gpu(cfg, steps, warmup, autotune=False):
     ctx = Context([cfg])
     if autotune:
         from paper_2308_13092_amd.autotune import autotune as tune
-        tune(ctx)
+        chosen, table = tune(ctx)
+        for setting, sec in table:
+            print(f"[autotune] {setting}: {sec * 1e3:.4f} ms/step", file=sys.stderr, flush=True)
+        print(f"[autotune] chosen {chosen}", file=sys.stderr, flush=True)
     ctx.step(warmup)
     torch.cuda.synchronize()
     d0 = ctx.diagnostics()
@@ -85,6 +88,58 @@ def run_gpu(cfg, steps, warmup, autotune=False):
     ctx.close()
     del ctx
     torch.cuda.empty_cache()
+    return out
+
+
+def run_sweep(steps, warmup, n_inst=256):
+    """Workload 4: the batched sweep of independent discharges, all advanced by
+    the same graph-replayed steps."""
+    import torch
+    from paper_2308_13092_amd import Context, configs
+    cfgs = configs.sweep(n_inst)
+    t0 = time.perf_counter()
+    ctx = Context(cfgs)
+    init_s = time.perf_counter() - t0
+    ctx.step(warmup)
+    torch.cuda.synchronize()
+    ps0 = sum(int(ctx.diagnostics(i)["particle_steps"]) for i in range(n_inst))
+    t0 = time.perf_counter()
+    ctx.step(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ps1 = sum(int(ctx.diagnostics(i)["particle_steps"]) for i in range(n_inst))
+    live = sum(int(sum(ctx.diagnostics(i)["n_live"])) for i in range(n_inst))
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+    return dict(value=(ps1 - ps0) / el, unit="particle-steps/s", instances=n_inst, steps=steps,
+                ms_per_step=1e3 * el / steps, live_particles=live, init_s=round(init_s, 2),
+                config="256 discharges from seed 13092: 64-1024 uniform cells, 5e4-2e6 particles "
+                       "(log-uniform), 100-500 V, 10-100 mTorr, dt = T_RF/(400-1000), FP32 state")
+
+
+def run_serving(n_req, scale, cycles, rate, slots):
+    """Workload 5 on a shortened trace: Poisson arrivals served with continuous
+    batching; p50 / p99 latency beside throughput."""
+    import torch
+    from paper_2308_13092_amd import configs
+    from paper_2308_13092_amd.serve import GpuBackend, Server, summarise
+    trace = configs.stream(n=n_req, rate=rate, scale=scale, cycles=cycles)
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(0.8 * free)
+    be = GpuBackend(n_slots=slots, pool_bytes=budget, precision=1)
+    srv = Server(be, n_slots=slots)
+    t0 = time.perf_counter()
+    reqs = srv.run(trace)
+    wall = time.perf_counter() - t0
+    be.close()
+    del be
+    torch.cuda.empty_cache()
+    out = summarise(reqs, wall)
+    out.update(unit_latency="s", slots=slots, pool_bytes=budget, device_steps=srv.device_steps,
+               trace=(f"{n_req} requests, Poisson arrivals at {rate}/s (seed 13093), 64-2048 cells, "
+                      f"{scale:g} x (1e5-8e6) particles, {cycles[0]}-{cycles[1]} RF cycles each, "
+                      f"FP32 state; shortened from the 256-request, 50-500-cycle stream"))
     return out
 
 
@@ -119,6 +174,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--sweep-steps", type=int, default=2000)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=64)
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the discharge "
@@ -155,6 +214,16 @@ def main():
                     fp32_speedup=r32["value"] / r64["value"])
         print(f"[bench] fp64: {r64['value']:.4g} p-s/s", file=sys.stderr, flush=True)
 
+    sweep = None
+    if not a.no_sweep:
+        sweep = run_sweep(a.sweep_steps, 100)
+        print(f"[bench] sweep: {sweep['value']:.4g} p-s/s", file=sys.stderr, flush=True)
+    serving = None
+    if not a.no_serve:
+        serving = run_serving(a.serve_requests, 0.1, (5, 20), 20.0, 256)
+        print(f"[bench] serving: p50 {serving['p50_s']:.3f} s, p99 {serving['p99_s']:.3f} s, "
+              f"{serving['throughput']:.4g} p-s/s", file=sys.stderr, flush=True)
+
     cpu = None if a.no_cpu else cpu_baseline()
     line = {
         "metric": "particle-steps/sec at 1 MI355X, FP32-state vs FP64 plain; p50/p99 sweep latency",
@@ -177,6 +246,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fp64_plain": fp64,
+        "batched_sweep": sweep,
+        "serving": serving,
         "status": r32["status"],
     }
     print(json.dumps(line))
