@@ -37,14 +37,41 @@ constexpr int kPPT = 4;                     // particles per thread per tile
 constexpr float kWalkLimit = 4194304.0f;    // |sigma| beyond 2^22 cells: out of any grid
 
 // ---------------------------------------------------------------------------
+// Values that are the same on every lane, made known as such to the compiler
+// (they then live in scalar registers).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uni(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ double uni(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xFFFFFFFFll));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// The grid parameters that locating and walking a particle need.  The
+// streaming kernel reads them once per segment into registers: read through
+// the instance table inside the particle loop they would be reloaded from
+// memory for every particle, since the loop's stores could alias the table.
+struct GridPar {
+  int N, periodic, uniform;
+  double dx;
+};
+__device__ __forceinline__ GridPar grid_par(const InstDev &I) {
+  return GridPar{I.N, I.bc == 1 ? 1 : 0, I.uniform, I.dx};
+}
+
+// ---------------------------------------------------------------------------
 // Locating positions (FP64 form) -- the deposit contract.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int locate64(const InstDev &I, const double *nodes, double x, double &xi) {
-  const int N = I.N;
+__device__ __forceinline__ int locate64(const GridPar &G, const double *nodes, double x, double &xi) {
+  const int N = G.N;
   int j;
   double f;
-  if (I.uniform) {
-    const double s = x / I.dx;
+  if (G.uniform) {
+    const double s = x / G.dx;
     const double jf = floor(s);
     j = (int)jf;
     if (j >= N) j = N - 1;
@@ -67,7 +94,7 @@ __device__ __forceinline__ int locate64(const InstDev &I, const double *nodes, d
 // it rounds up to 1 (kept below 1 in the last cell of a bounded grid).
 __device__ __forceinline__ void to_state32(const InstDev &I, double x, int &cell, float &off) {
   double xi;
-  int j = locate64(I, I.nodes, x, xi);
+  int j = locate64(grid_par(I), I.nodes, x, xi);
   float o = (float)xi;
   if (o >= 1.0f) {
     if (j + 1 < I.N) { j += 1; o = 0.0f; }
@@ -102,15 +129,15 @@ __device__ __forceinline__ void weights32(float off, int64_t &w0, int64_t &w1) {
 // (low 16 bits) and last (high 16 bits) cell of its run of equal widths; a
 // uniform grid is one run.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int walk32(const InstDev &I, const float *rf, const float *rb,
+__device__ __forceinline__ int walk32(const GridPar &G, const float *rf, const float *rb,
                                       const int *run, int &j, float &sig) {
-  const int N = I.N;
-  const bool periodic = I.bc == 1;
+  const int N = G.N;
+  const bool periodic = G.periodic != 0;
   if (!(fabsf(sig) < kWalkLimit)) {
     if (sig != sig || periodic) return 2;
     return sig < 0.0f ? -1 : 1;
   }
-  if (I.uniform) {
+  if (G.uniform) {
     if (sig < 0.0f || sig >= 1.0f) {
       const float m = floorf(sig);
       float r = sig - m;
@@ -422,7 +449,7 @@ __device__ void emit_secondary(const InstDev &I, InstState &S, Smem &sm, uint64_
     j = cell;
     xi = (double)off;
   } else {
-    j = locate64(I, I.nodes, x, xi);
+    j = locate64(grid_par(I), I.nodes, x, xi);
   }
   const int64_t idx = append_slot(I, S, 0);
   if (idx < 0) return;
@@ -539,6 +566,12 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
   int *gq = nullptr;
   bool deposit_on = false;
   unsigned long long live_here = 0;
+  // Per-segment constants, in scalar registers (see GridPar).
+  GridPar G{0, 0, 0, 0.0};
+  int gather = 0;
+  bool coll = false, due_eedf = false;
+  float qmdt32 = 0.0f, hq32 = 0.0f;
+  double qmdt = 0.0, hq = 0.0, dt = 0.0, L = 0.0;
 
   // Append this lane's entry (if any) to the wavefront queue; move full
   // groups of 64 (or, at the end of a segment, all) to the segment's HBM queue.
@@ -599,6 +632,16 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
       P = F::view(I, sp, Sp->parity);
       gq = I.queue[sp];
       const int par = (int)(k & 1);
+      G = GridPar{uni(I.N), uni(I.bc == 1 ? 1 : 0), uni(I.uniform), uni(I.dx)};
+      gather = uni(I.gather);
+      coll = (MODE == M_MCC || MODE == M_FUSED) && I.nudt[sp] > 0.0;
+      due_eedf = (MODE == M_PUSH || MODE == M_FUSED) && sp == 0 && eedf_due(I, k);
+      qmdt32 = uni(I.qmdt32[sp]);
+      hq32 = uni(I.hq32[sp]);
+      qmdt = uni(I.qmdt[sp]);
+      hq = uni(I.hq[sp]);
+      dt = uni(I.dt);
+      L = uni(I.L);
       deposit_on = (MODE == M_DEPOSIT) || (MODE == M_FUSED);
       A_out = (MODE == M_DEPOSIT) ? I.A[par][sp] : I.A[par ^ 1][sp];
       if (MODE != M_MCC) {
@@ -606,9 +649,9 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
         if constexpr (F::prec == 1) {
           if (MODE != M_DEPOSIT) {
             for (int j = t; j < ne; j += BLOCK) sE32[j] = I.E32[j];
+            for (int j = t; j < N; j += BLOCK) sDtoh[j] = I.uniform ? I.dtoh32u : I.dtoh32[j];
             if (!I.uniform) {
               for (int j = t; j < N; j += BLOCK) {
-                sDtoh[j] = I.dtoh32[j];
                 sRf[j] = I.rf32[j];
                 sRb[j] = I.rb32[j];
                 sRun[j] = I.runs[j];
@@ -628,8 +671,6 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
     const int64_t base = (tile - seg_first) * TILE;
     const int64_t i0 = base + (int64_t)t * kPPT;
     const bool full = i0 + kPPT <= ext;
-    const bool due_eedf = (MODE == M_PUSH || MODE == M_FUSED) && sp == 0 && eedf_due(I, k);
-    const bool coll = (MODE == M_MCC || MODE == M_FUSED) && I.nudt[sp] > 0.0;
     DepAcc dep;
     dep.init();
     bool want[kPPT];
@@ -681,22 +722,21 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
           weights32(o[q], w0, w1);
           dep.add(sA, c[q], w0, w1);
         } else if constexpr (MODE == M_PULLBACK) {
-          const float e = (I.gather == 0) ? sE32[c[q]]
-                                          : ((1.0f - o[q]) * sE32[c[q]]) + (o[q] * sE32[c[q] + 1]);
-          vn[q] = vx[q] - I.hq32[sp] * e;
+          const float e = (gather == 0) ? sE32[c[q]]
+                                        : ((1.0f - o[q]) * sE32[c[q]]) + (o[q] * sE32[c[q] + 1]);
+          vn[q] = vx[q] - hq32 * e;
         } else if constexpr (MODE == M_MCC) {
           want[q] = coll && kn[q] <= k;
           went[q] = qentry(ii, 0);
         } else {
           live_here += 1;
           const int j = c[q];
-          const float e = (I.gather == 0) ? sE32[j]
-                                          : ((1.0f - o[q]) * sE32[j]) + (o[q] * sE32[j + 1]);
-          const float v1 = vx[q] + I.qmdt32[sp] * e;
-          const float dtoh = I.uniform ? I.dtoh32u : sDtoh[j];
-          float sig = o[q] + v1 * dtoh;
+          const float e = (gather == 0) ? sE32[j]
+                                        : ((1.0f - o[q]) * sE32[j]) + (o[q] * sE32[j + 1]);
+          const float v1 = vx[q] + qmdt32 * e;
+          float sig = o[q] + v1 * sDtoh[j];
           int jj = j;
-          const int wall = walk32(I, sRf, sRb, sRun, jj, sig);
+          const int wall = walk32(G, sRf, sRb, sRun, jj, sig);
           vn[q] = v1;
           if (wall != 0 || v1 != v1) {
             cn[q] = -1;
@@ -783,35 +823,35 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
         const int ii = (int)(i0 + q);
         if constexpr (MODE == M_DEPOSIT) {
           double xi;
-          const int j = locate64(I, sNodes, x[q], xi);
+          const int j = locate64(G, sNodes, x[q], xi);
           int64_t w0, w1;
           weights(xi, w0, w1);
           dep.add(sA, j, w0, w1);
         } else if constexpr (MODE == M_PULLBACK) {
           double xi;
-          const int j = locate64(I, sNodes, x[q], xi);
-          const double e = (I.gather == 0) ? sE64[j] : (1.0 - xi) * sE64[j] + xi * sE64[j + 1];
-          vn[q] = vx[q] - I.hq[sp] * e;
+          const int j = locate64(G, sNodes, x[q], xi);
+          const double e = (gather == 0) ? sE64[j] : (1.0 - xi) * sE64[j] + xi * sE64[j + 1];
+          vn[q] = vx[q] - hq * e;
         } else if constexpr (MODE == M_MCC) {
           want[q] = coll && kn[q] <= k;
           went[q] = qentry(ii, 0);
         } else {
           live_here += 1;
           double xi;
-          const int j = locate64(I, sNodes, x[q], xi);
-          const double e = (I.gather == 0) ? sE64[j] : (1.0 - xi) * sE64[j] + xi * sE64[j + 1];
-          const double v1 = vx[q] + I.qmdt[sp] * e;
-          double x1 = x[q] + v1 * I.dt;
+          const int j = locate64(G, sNodes, x[q], xi);
+          const double e = (gather == 0) ? sE64[j] : (1.0 - xi) * sE64[j] + xi * sE64[j + 1];
+          const double v1 = vx[q] + qmdt * e;
+          double x1 = x[q] + v1 * dt;
           vn[q] = v1;
           int wall = 0;
-          if (I.bc == 1) {
-            if (!(fabs(x1) < 4.0 * I.L)) wall = 2;
+          if (G.periodic) {
+            if (!(fabs(x1) < 4.0 * L)) wall = 2;
             else {
-              while (x1 < 0.0) x1 = x1 + I.L;
-              while (x1 >= I.L) x1 = x1 - I.L;
+              while (x1 < 0.0) x1 = x1 + L;
+              while (x1 >= L) x1 = x1 - L;
             }
-          } else if (!(x1 >= 0.0 && x1 < I.L)) {
-            wall = (x1 < 0.0) ? -1 : ((x1 >= I.L) ? 1 : 2);
+          } else if (!(x1 >= 0.0 && x1 < L)) {
+            wall = (x1 < 0.0) ? -1 : ((x1 >= L) ? 1 : 2);
           }
           if (wall != 0) {
             xn[q] = -1.0;
@@ -827,7 +867,7 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
               eedf_sample(I, x1, v1, P.vy[ii], P.vz[ii]);
             if constexpr (MODE == M_FUSED) {
               double xi1;
-              const int j1 = locate64(I, sNodes, x1, xi1);
+              const int j1 = locate64(G, sNodes, x1, xi1);
               int64_t w0, w1;
               weights(xi1, w0, w1);
               dep.add(sA, j1, w0, w1);
@@ -927,7 +967,7 @@ __device__ void drain_one(const InstDev &I, InstState &S, Smem &sm, int sp, int 
           j = cc;
           xi = (double)oo;
         } else {
-          j = locate64(I, I.nodes, xx, xi);
+          j = locate64(grid_par(I), I.nodes, xx, xi);
         }
         int64_t w0, w1;
         weights(xi, w0, w1);
