@@ -87,6 +87,15 @@ struct InstDev {
   char *pbuf[2][2];            // [species][buffer]
 };
 
+// The instance table is written by the host between kernels and only read on
+// the device.  Kernels read it through the constant address space, so the
+// compiler may use scalar loads and keep its fields in registers across the
+// kernels' stores to other memory (through a generic pointer every field
+// would be reloaded after every store, since the store might alias it).
+#define ECPIC_CONST __attribute__((address_space(4)))
+typedef const ECPIC_CONST InstDev CInst;
+__device__ __forceinline__ CInst *cinst(const InstDev *p) { return (CInst *)p; }
+
 struct InstState {
   int64_t k;
   int32_t status, parity;

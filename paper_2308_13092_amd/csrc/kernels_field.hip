@@ -77,7 +77,7 @@ k_field(const InstDev *__restrict__ insts, InstState *__restrict__ states, int m
   __shared__ int64_t tmpi[kFB];
   __shared__ double tmpd[kFB];
 
-  const InstDev &I = insts[blockIdx.x];
+  CInst &I = cinst(insts)[blockIdx.x];
   InstState &S = states[blockIdx.x];
   if (!I.active || S.frozen != 0) return;
   if (I.k_stop > 0 && S.k >= I.k_stop) return;

@@ -59,7 +59,7 @@ struct GridPar {
   int N, periodic, uniform;
   double dx;
 };
-__device__ __forceinline__ GridPar grid_par(const InstDev &I) {
+__device__ __forceinline__ GridPar grid_par(CInst &I) {
   return GridPar{I.N, I.bc == 1 ? 1 : 0, I.uniform, I.dx};
 }
 
@@ -92,7 +92,7 @@ __device__ __forceinline__ int locate64(const GridPar &G, const double *nodes, d
 
 // FP32 state of an FP64 position: off = (float) xi, moved to the next cell when
 // it rounds up to 1 (kept below 1 in the last cell of a bounded grid).
-__device__ __forceinline__ void to_state32(const InstDev &I, double x, int &cell, float &off) {
+__device__ __forceinline__ void to_state32(CInst &I, double x, int &cell, float &off) {
   double xi;
   int j = locate64(grid_par(I), I.nodes, x, xi);
   float o = (float)xi;
@@ -118,99 +118,101 @@ __device__ __forceinline__ void weights32(float off, int64_t &w0, int64_t &w1) {
 }
 
 // ---------------------------------------------------------------------------
-// FP32 cell walk.  Returns 0 (inside), -1 / +1 (left the bounded grid on that
-// side) or 2 (non-finite or runaway).  The contract is the cell-by-cell walk
+// FP32 cell walk.  The contract is the cell-by-cell walk
 //   while sigma < 0:  j -= 1 (wrap), sigma = 1 + sigma * (h_{j+1}/h_j)
 //   while sigma >= 1: sigma = (sigma - 1) * (h_j/h_{j+1}), j += 1 (wrap)
-// in FP32.  Inside a run of equal cells every step is sigma -= 1 (exact) or
-// sigma += 1 (exact while sigma <= -1), so m steps collapse into one
-// operation with the same result: sigma - m moving right, and fl(sigma + m)
-// moving left (only the last step rounds).  `run` packs, per cell, the first
-// (low 16 bits) and last (high 16 bits) cell of its run of equal widths; a
-// uniform grid is one run.
+// in FP32, with the ratios rounded to FP32.  Inside a run of cells whose FP32
+// ratios are exactly 1 every step is sigma -= 1 (exact) or sigma += 1 (exact
+// while sigma <= -1), so m steps collapse into one operation with the same
+// result: sigma - m moving right, and fl(sigma + m) moving left (only the last
+// step rounds; if it rounds up to 1 the contract's next step moves one cell
+// right to offset 0).  The only ratios that are not 1 are met when leaving a
+// run: h_hi/h_{hi+1} at its last cell and h_lo/h_{lo-1} before its first.
+//
+// Each cell's LDS entry is {dt/h_j, run (first | last << 16), ratio leaving
+// the run forward, ratio leaving it backward}; a periodic grid uses runs of
+// one cell (its walk wraps).  One walk step from cell j uses only j's entry:
+// the collapsed move inside the run or, when sigma leaves the run, the move to
+// its end and across into the next cell.  Almost every particle is done after
+// the first step, which needs no data beyond the entry already read for it.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int walk32(const GridPar &G, const float *rf, const float *rb,
-                                      const int *run, int &j, float &sig) {
-  const int N = G.N;
-  const bool periodic = G.periodic != 0;
-  if (!(fabsf(sig) < kWalkLimit)) {
-    if (sig != sig || periodic) return 2;
-    return sig < 0.0f ? -1 : 1;
-  }
-  if (G.uniform) {
-    if (sig < 0.0f || sig >= 1.0f) {
-      const float m = floorf(sig);
-      float r = sig - m;
-      int jj = j + (int)m;
-      if (r >= 1.0f) { r = 0.0f; jj += 1; }
-      if (periodic) {
-        jj %= N;
-        if (jj < 0) jj += N;
-      } else if (jj < 0) {
-        return -1;
-      } else if (jj >= N) {
-        return 1;
-      }
-      j = jj;
-      sig = r;
+enum : int { W_IN = 0, W_LEFT = -1, W_RIGHT = 1, W_BAD = 2, W_MORE = 3 };
+
+__device__ __forceinline__ int walk_step(const int4 T, int N, int periodic, int &j, float &sig) {
+  const int lo = T.y & 0xFFFF, hi = T.y >> 16;
+  if (sig >= 1.0f) {
+    const float m = floorf(sig);
+    const int avail = hi - j;
+    if (m <= (float)avail) {
+      j += (int)m;
+      sig = sig - m;
+      return W_IN;
     }
-    return 0;
-  }
-  int guard = 0;
-  if (periodic) {
-    while (sig < 0.0f) {
-      j -= 1;
-      if (j < 0) j += N;
-      const float tt = sig * rb[j];
-      sig = 1.0f + tt;
-      if (++guard > 4 * N + 64) return 2;
+    float r = sig - (float)avail;       // exact: at the run's last cell
+    r = (r - 1.0f) * __int_as_float(T.z);
+    j = hi + 1;
+    if (j >= N) {
+      if (!periodic) return W_RIGHT;
+      j -= N;
     }
-    while (sig >= 1.0f) {
-      sig = (sig - 1.0f) * rf[j];
+    sig = r;
+    return (r >= 1.0f) ? W_MORE : W_IN;
+  }
+  const float m = -floorf(sig);
+  const int avail = j - lo;
+  if (m <= (float)avail) {
+    j -= (int)m;
+    sig = sig + m;
+    if (sig >= 1.0f) {   // rounded up to the right edge: next cell, offset 0
+      sig = 0.0f;
       j += 1;
-      if (j >= N) j -= N;
-      if (++guard > 4 * N + 64) return 2;
     }
-    return 0;
+    return W_IN;
   }
-  while (sig < 0.0f) {
-    const int lo = run[j] & 0xFFFF;
-    if (lo < j) {
-      const float m = -floorf(sig);
-      const int avail = j - lo;
-      if (m <= (float)avail) {
-        j -= (int)m;
-        sig = sig + m;
-        continue;
-      }
-      sig = sig + (float)avail;
-      j = lo;
-    }
-    j -= 1;
-    if (j < 0) return -1;
-    const float tt = sig * rb[j];
-    sig = 1.0f + tt;
-    if (++guard > 4 * N + 64) return 2;
+  float r = sig + (float)avail;         // exact: at the run's first cell
+  j = lo - 1;
+  if (j < 0) {
+    if (!periodic) return W_LEFT;
+    j += N;
   }
-  while (sig >= 1.0f) {
-    const int hi = run[j] >> 16;
-    if (hi > j) {
-      const float m = floorf(sig);
-      const int avail = hi - j;
-      if (m <= (float)avail) {
-        j += (int)m;
-        sig = sig - m;
-        continue;
-      }
-      sig = sig - (float)avail;
-      j = hi;
-    }
-    sig = (sig - 1.0f) * rf[j];
-    j += 1;
-    if (j >= N) return 1;
-    if (++guard > 4 * N + 64) return 2;
+  const float tt = r * __int_as_float(T.w);
+  r = 1.0f + tt;
+  sig = r;
+  return (r >= 0.0f && r < 1.0f) ? W_IN : W_MORE;
+}
+
+// A uniform grid is one run without wrap-around ratios: the whole walk is one
+// floor (bounded), or one floor and a wrap (periodic).
+__device__ __forceinline__ int walk_uniform(int N, int periodic, int &j, float &sig) {
+  const float m = floorf(sig);
+  float r = sig - m;
+  int jj = j + (int)m;
+  if (r >= 1.0f) {
+    r = 0.0f;
+    jj += 1;
   }
-  return 0;
+  if (periodic) {
+    jj %= N;
+    if (jj < 0) jj += N;
+  } else if (jj < 0) {
+    return W_LEFT;
+  } else if (jj >= N) {
+    return W_RIGHT;
+  }
+  j = jj;
+  sig = r;
+  return W_IN;
+}
+
+// First walk step of a particle whose sigma left [0, 1): W_IN, W_LEFT/W_RIGHT,
+// W_BAD (non-finite, or beyond any grid in a periodic box) or W_MORE.
+__device__ __forceinline__ int walk_first(const GridPar &G, const int4 T, int &j, float &sig) {
+  if (!(fabsf(sig) < kWalkLimit)) {
+    if (sig != sig || G.periodic) return W_BAD;
+    return sig < 0.0f ? W_LEFT : W_RIGHT;
+  }
+  if (G.uniform) return walk_uniform(G.N, G.periodic, j, sig);
+  return walk_step(T, G.N, G.periodic, j, sig);
 }
 
 // ---------------------------------------------------------------------------
@@ -230,7 +232,7 @@ __device__ __forceinline__ void iso_dir(double ua, double ub, double &dx, double
   dy = st * cos(a);
   dz = st * sin(a);
 }
-__device__ __forceinline__ void gas_velocity(const InstDev &I, uint64_t id, int64_t k, int s,
+__device__ __forceinline__ void gas_velocity(CInst &I, uint64_t id, int64_t k, int s,
                                              double &gx, double &gy, double &gz) {
   const uint4 g = philox((uint32_t)k, TAG_GAS | (uint32_t)(s << 8), I.seed, id);
   double z0, z1, z2, z3;
@@ -243,7 +245,7 @@ __device__ __forceinline__ void gas_velocity(const InstDev &I, uint64_t id, int6
 
 // Electron null collision.  Returns the process (0 null, 1 elastic,
 // 2 excitation, 3 ionisation); ej receives the ejected electron's velocity.
-__device__ int collide_electron(const InstDev &I, uint64_t id, int64_t k, double &vx, double &vy,
+__device__ int collide_electron(CInst &I, uint64_t id, int64_t k, double &vx, double &vy,
                                 double &vz, bool &bound, double ej[3]) {
   const uint4 r = philox((uint32_t)k, TAG_COLL, I.seed, id);
   const double u1 = u32d(r.x), u2 = u32d(r.y), u3 = u32d(r.z);
@@ -286,7 +288,7 @@ __device__ int collide_electron(const InstDev &I, uint64_t id, int64_t k, double
 }
 
 // Ion charge exchange with a gas atom drawn from the gas Maxwellian.
-__device__ bool collide_ion(const InstDev &I, uint64_t id, int64_t k, double &vx, double &vy,
+__device__ bool collide_ion(CInst &I, uint64_t id, int64_t k, double &vx, double &vy,
                             double &vz, bool &bound) {
   const uint4 r = philox((uint32_t)k, TAG_COLL | (1u << 8), I.seed, id);
   const double u1 = u32d(r.x);
@@ -355,11 +357,11 @@ __device__ __forceinline__ void set_status(InstState &S, int bits) {
   atomicOr(&S.status, bits);
 }
 
-__device__ __forceinline__ bool eedf_due(const InstDev &I, int64_t k) {
+__device__ __forceinline__ bool eedf_due(CInst &I, int64_t k) {
   return I.eedf_every > 0 && k >= I.avg_start && ((k - I.avg_start) % I.eedf_every) == 0;
 }
 
-__device__ __forceinline__ void eedf_sample(const InstDev &I, double x, double vx, double vy,
+__device__ __forceinline__ void eedf_sample(CInst &I, double x, double vx, double vy,
                                             double vz) {
   if (!(fabs(x - I.eedf_centre) < I.eedf_half)) return;
   const double eps = kHALF_ME_OVER_QE * ((vx * vx + vy * vy) + vz * vz);
@@ -370,7 +372,7 @@ __device__ __forceinline__ void eedf_sample(const InstDev &I, double x, double v
 // Reserve a slot for a new particle of species s; -1 when the segment is full.
 // All lanes of the wavefront that call this together (same instance and
 // species) share one atomic: the first takes the whole group's slots.
-__device__ __forceinline__ int64_t append_slot(const InstDev &I, InstState &S, int s) {
+__device__ __forceinline__ int64_t append_slot(CInst &I, InstState &S, int s) {
   const unsigned long long active = __ballot(true);
   const int lane = __lane_id();
   const int leader = __ffsll((long long)active) - 1;
@@ -393,18 +395,18 @@ struct F32 {
   static constexpr int prec = 1;
   using V = float;
   using View = P32;
-  static __device__ View view(const InstDev &I, int s, int buf) { return view32(I.pbuf[s][buf], I.cap[s]); }
+  static __device__ View view(CInst &I, int s, int buf) { return view32(I.pbuf[s][buf], I.cap[s]); }
 };
 struct F64 {
   static constexpr int prec = 0;
   using V = double;
   using View = P64;
-  static __device__ View view(const InstDev &I, int s, int buf) { return view64(I.pbuf[s][buf], I.cap[s]); }
+  static __device__ View view(CInst &I, int s, int buf) { return view64(I.pbuf[s][buf], I.cap[s]); }
 };
 
 // Write a new particle (SEE electron or ionisation product).
 template <class F>
-__device__ void write_new(const InstDev &I, typename F::View P, int64_t idx, double x, int cell,
+__device__ void write_new(CInst &I, typename F::View P, int64_t idx, double x, int cell,
                          float off, double vx, double vy, double vz, uint64_t id, int32_t kn) {
   if constexpr (F::prec == 1) {
     P.cell[idx] = cell;
@@ -425,7 +427,7 @@ __device__ void write_new(const InstDev &I, typename F::View P, int64_t idx, dou
 // Secondary emission by an ion absorbed at `wall` during step k.  The new
 // electron goes straight into the electron deposit of step k+1 when `dep`.
 template <class F>
-__device__ void emit_secondary(const InstDev &I, InstState &S, Smem &sm, uint64_t ion_id, int wall,
+__device__ void emit_secondary(CInst &I, InstState &S, Smem &sm, uint64_t ion_id, int wall,
                                int64_t k, int buf, bool dep, int64_t *A_next_e) {
   const uint4 r = philox((uint32_t)k, TAG_SEE | (1u << 8), I.seed, ion_id);
   if (!(u32d(r.x) < I.gamma_see)) return;
@@ -490,7 +492,7 @@ __device__ int64_t segment_prefix(const InstDev *insts, const InstState *states,
   const int nseg = 2 * n_inst;
   const int t = threadIdx.x;
   for (int s = t; s < nseg; s += BLOCK) {
-    const InstDev &I = insts[s >> 1];
+    CInst &I = cinst(insts)[s >> 1];
     const InstState &S = states[s >> 1];
     const int sp = s & 1;
     const bool ok = I.active && S.frozen == 0 && sp < I.nsp && !(I.k_stop > 0 && S.k >= I.k_stop);
@@ -534,17 +536,15 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
   const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int np1 = max_n + 1;
   int64_t *sA = reinterpret_cast<int64_t *>(dsm);
-  // FP32: E f32[np1], dt/h f32[max_n], forward and backward ratios f32[max_n],
-  // runs of equal cells i32[max_n].
-  float *sE32 = reinterpret_cast<float *>(sA + np1);
-  float *sDtoh = sE32 + np1;
-  float *sRf = sDtoh + max_n;
-  float *sRb = sRf + max_n;
-  int *sRun = reinterpret_cast<int *>(sRb + max_n);
+  // FP32: the walk entry of every cell int4[max_n] (see walk_step), then E
+  // f32[np1].
+  const size_t a_bytes = ((size_t)np1 * 8 + 15) & ~(size_t)15;
+  int4 *sT = reinterpret_cast<int4 *>(dsm + a_bytes);
+  float *sE32 = reinterpret_cast<float *>(sT + max_n);
   // FP64: E f64[np1], nodes f64[np1].
   double *sE64 = reinterpret_cast<double *>(sA + np1);
   double *sNodes = sE64 + np1;
-  const size_t tables = (F::prec == 1) ? (size_t)np1 * 12 + (size_t)max_n * 16 : (size_t)np1 * 24;
+  const size_t tables = (F::prec == 1) ? a_bytes + (size_t)max_n * 16 + (size_t)np1 * 4 : (size_t)np1 * 24;
   int *wq = reinterpret_cast<int *>(dsm + ((tables + 15) & ~(size_t)15)) + (t >> 6) * kWaveQ;
   int wq_n = 0;   // entries in this wavefront's queue (wavefront-uniform)
 
@@ -557,7 +557,7 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
   const int64_t t1 = T * (blockIdx.x + 1) / gridDim.x;
 
   int seg = -1;
-  const InstDev *Ip = nullptr;
+  CInst *Ip = nullptr;
   InstState *Sp = nullptr;
   int sp = 0, N = 0;
   int64_t k = 0, ext = 0, seg_first = 0;
@@ -621,10 +621,10 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
     if (s != seg) {
       if (seg >= 0) flush();
       seg = s;
-      Ip = &insts[seg >> 1];
+      Ip = &cinst(insts)[seg >> 1];
       Sp = &states[seg >> 1];
       sp = seg & 1;
-      const InstDev &I = *Ip;
+      CInst &I = *Ip;
       N = I.N;
       k = Sp->k;
       ext = Sp->extent[sp];
@@ -649,12 +649,17 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
         if constexpr (F::prec == 1) {
           if (MODE != M_DEPOSIT) {
             for (int j = t; j < ne; j += BLOCK) sE32[j] = I.E32[j];
-            for (int j = t; j < N; j += BLOCK) sDtoh[j] = I.uniform ? I.dtoh32u : I.dtoh32[j];
-            if (!I.uniform) {
-              for (int j = t; j < N; j += BLOCK) {
-                sRf[j] = I.rf32[j];
-                sRb[j] = I.rb32[j];
-                sRun[j] = I.runs[j];
+            if (MODE != M_PULLBACK) {
+              if (I.uniform) {
+                for (int j = t; j < N; j += BLOCK) sT[j] = make_int4(__float_as_int(I.dtoh32u), 0, 0, 0);
+              } else {
+                const bool per = I.bc == 1;
+                for (int j = t; j < N; j += BLOCK) {
+                  const int run = per ? (j | (j << 16)) : I.runs[j];
+                  const int lo = run & 0xFFFF, hi = run >> 16;
+                  sT[j] = make_int4(__float_as_int(I.dtoh32[j]), run, __float_as_int(I.rf32[hi]),
+                                    __float_as_int(I.rb32[lo > 0 ? lo - 1 : N - 1]));
+                }
               }
             }
           }
@@ -667,7 +672,7 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
       }
       __syncthreads();
     }
-    const InstDev &I = *Ip;
+    CInst &I = *Ip;
     const int64_t base = (tile - seg_first) * TILE;
     const int64_t i0 = base + (int64_t)t * kPPT;
     const bool full = i0 + kPPT <= ext;
@@ -708,6 +713,79 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
       }
       int cn[kPPT];
       float on[kPPT], vn[kPPT];
+      if constexpr (MODE == M_PUSH || MODE == M_FUSED) {
+        // Gather, push and first walk step of the thread's particles; then
+        // the rare walks that go on (across more than one run boundary).
+        int st[kPPT];
+        bool more = false;
+#pragma unroll
+        for (int q = 0; q < kPPT; ++q) {
+          cn[q] = c[q];
+          on[q] = o[q];
+          vn[q] = vx[q];
+          st[q] = W_IN;
+          if (c[q] < 0) continue;
+          const int j = c[q];
+          const float e = (gather == 0) ? sE32[j]
+                                        : ((1.0f - o[q]) * sE32[j]) + (o[q] * sE32[j + 1]);
+          const float v1 = vx[q] + qmdt32 * e;
+          const int4 T = sT[j];
+          float sig = o[q] + v1 * __int_as_float(T.x);
+          int jj = j;
+          if (sig < 0.0f || sig >= 1.0f) st[q] = walk_first(G, T, jj, sig);
+          vn[q] = v1;
+          cn[q] = jj;
+          on[q] = sig;
+          more |= st[q] == W_MORE;
+        }
+        if (__ballot(more) != 0) {
+#pragma unroll
+          for (int q = 0; q < kPPT; ++q) {
+            int guard = 0;
+            while (st[q] == W_MORE) {
+              if (++guard > 4 * G.N + 64) {
+                st[q] = W_BAD;
+                break;
+              }
+              st[q] = walk_step(sT[cn[q]], G.N, G.periodic, cn[q], on[q]);
+            }
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < kPPT; ++q) {
+          want[q] = false;
+          went[q] = 0;
+          if (c[q] < 0) continue;   // dead slot
+          live_here += 1;
+          const int ii = (int)(i0 + q);
+          const int wall = st[q];
+          const float v1 = vn[q];
+          if (wall != W_IN || v1 != v1) {
+            cn[q] = -1;
+            on[q] = o[q];
+            want[q] = true;
+            went[q] = qentry(ii, (wall == W_BAD || v1 != v1) ? 3 : (wall < 0 ? 1 : 2));
+          } else {
+            const int jj = cn[q];
+            const float sig = on[q];
+            if (MODE == M_FUSED && coll && kn[q] <= k) {
+              want[q] = true;
+              went[q] = qentry(ii, 0);
+            }
+            if (due_eedf) {
+              const double x = I.uniform ? ((double)jj * I.dx + (double)sig * I.dx)
+                                         : (I.nodes[jj] + (double)sig * I.h[jj]);
+              if (fabs(x - I.eedf_centre) < I.eedf_half)
+                eedf_sample(I, x, (double)v1, (double)P.vy[ii], (double)P.vz[ii]);
+            }
+            if constexpr (MODE == M_FUSED) {
+              int64_t w0, w1;
+              weights32(sig, w0, w1);
+              dep.add(sA, jj, w0, w1);
+            }
+          }
+        }
+      } else {
 #pragma unroll
       for (int q = 0; q < kPPT; ++q) {
         want[q] = false;
@@ -728,40 +806,8 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
         } else if constexpr (MODE == M_MCC) {
           want[q] = coll && kn[q] <= k;
           went[q] = qentry(ii, 0);
-        } else {
-          live_here += 1;
-          const int j = c[q];
-          const float e = (gather == 0) ? sE32[j]
-                                        : ((1.0f - o[q]) * sE32[j]) + (o[q] * sE32[j + 1]);
-          const float v1 = vx[q] + qmdt32 * e;
-          float sig = o[q] + v1 * sDtoh[j];
-          int jj = j;
-          const int wall = walk32(G, sRf, sRb, sRun, jj, sig);
-          vn[q] = v1;
-          if (wall != 0 || v1 != v1) {
-            cn[q] = -1;
-            want[q] = true;
-            went[q] = qentry(ii, (wall == 2 || v1 != v1) ? 3 : (wall < 0 ? 1 : 2));
-          } else {
-            cn[q] = jj;
-            on[q] = sig;
-            if (MODE == M_FUSED && coll && kn[q] <= k) {
-              want[q] = true;
-              went[q] = qentry(ii, 0);
-            }
-            if (due_eedf) {
-              const double x = I.uniform ? ((double)jj * I.dx + (double)sig * I.dx)
-                                         : (I.nodes[jj] + (double)sig * I.h[jj]);
-              if (fabs(x - I.eedf_centre) < I.eedf_half)
-                eedf_sample(I, x, (double)v1, (double)P.vy[ii], (double)P.vz[ii]);
-            }
-            if constexpr (MODE == M_FUSED) {
-              int64_t w0, w1;
-              weights32(sig, w0, w1);
-              dep.add(sA, jj, w0, w1);
-            }
-          }
         }
+      }
       }
       if constexpr (MODE == M_DEPOSIT || MODE == M_FUSED) dep.flush(sA);
       if constexpr (MODE == M_PUSH || MODE == M_FUSED || MODE == M_PULLBACK) {
@@ -909,7 +955,7 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
 // null-collision candidate (collision, ionisation products, next candidate
 // step).  Products go straight into the deposit of step k+1 in the fused pass.
 template <class F, int MODE>
-__device__ void drain_one(const InstDev &I, InstState &S, Smem &sm, int sp, int buf, int64_t k,
+__device__ void drain_one(CInst &I, InstState &S, Smem &sm, int sp, int buf, int64_t k,
                           typename F::View P, int entry) {
   const int64_t i = entry & kQMask;
   const int kind = (int)((unsigned)entry >> kQShift);
@@ -1018,7 +1064,7 @@ k_drain(const InstDev *__restrict__ insts, InstState *__restrict__ states, int n
       seg = s;
       Sp = &states[seg >> 1];
     }
-    const InstDev &I = insts[seg >> 1];
+    CInst &I = cinst(insts)[seg >> 1];
     const int sp = seg & 1;
     const int64_t e = (tile - sm.seg_prefix[seg]) * BLOCK + t;
     if (e < (int64_t)Sp->qcount[sp]) {
@@ -1036,7 +1082,7 @@ template <int MODE>
 __global__ void __launch_bounds__(256)
 k_finalize(const InstDev *__restrict__ insts, InstState *__restrict__ states, int n_inst) {
   for (int i = threadIdx.x; i < n_inst; i += blockDim.x) {
-    const InstDev &I = insts[i];
+    CInst &I = cinst(insts)[i];
     InstState &S = states[i];
     if (!I.active || S.frozen != 0 || (I.k_stop > 0 && S.k >= I.k_stop)) continue;
     for (int s = 0; s < I.nsp; ++s) {
@@ -1074,7 +1120,7 @@ template <class F>
 __global__ void __launch_bounds__(256)
 k_init(const InstDev *__restrict__ insts, InstState *__restrict__ states, int inst, int s,
        double t_ev) {
-  const InstDev &I = insts[inst];
+  CInst &I = cinst(insts)[inst];
   const int64_t n = I.n_init[s];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -1107,7 +1153,7 @@ template <class F>
 __global__ void __launch_bounds__(256)
 k_diag(const InstDev *__restrict__ insts, const InstState *__restrict__ states, int inst,
        unsigned long long *__restrict__ out) {
-  const InstDev &I = insts[inst];
+  CInst &I = cinst(insts)[inst];
   const InstState &S = states[inst];
   for (int s = 0; s < I.nsp; ++s) {
     typename F::View P = F::view(I, s, S.parity);
@@ -1141,7 +1187,7 @@ k_diag(const InstDev *__restrict__ insts, const InstState *__restrict__ states, 
 }
 
 __global__ void k_zero_deposit(const InstDev *__restrict__ insts, const InstState *__restrict__ states) {
-  const InstDev &I = insts[blockIdx.x];
+  CInst &I = cinst(insts)[blockIdx.x];
   const InstState &S = states[blockIdx.x];
   if (!I.active) return;
   const int par = (int)(S.k & 1);
@@ -1156,7 +1202,8 @@ __global__ void k_zero_deposit(const InstDev *__restrict__ insts, const InstStat
 // ---------------------------------------------------------------------------
 size_t particle_lds_bytes(int prec, int max_n, int block) {
   const size_t np1 = (size_t)max_n + 1;
-  const size_t tables = (prec == 1) ? np1 * 12 + (size_t)max_n * 16 : np1 * 24;
+  const size_t tables =
+      (prec == 1) ? ((np1 * 8 + 15) & ~(size_t)15) + (size_t)max_n * 16 + np1 * 4 : np1 * 24;
   const size_t q = (size_t)(block / 64) * kWaveQ * sizeof(int);
   return ((tables + 15) & ~(size_t)15) + q;
 }

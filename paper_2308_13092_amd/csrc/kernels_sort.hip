@@ -25,12 +25,12 @@ struct SortSmem {
   int seg_prefix[2 * kMaxInst + 1];
 };
 
-__device__ __forceinline__ int key_of(const InstDev &I, const P32 &P, int64_t i, const double *,
+__device__ __forceinline__ int key_of(CInst &I, const P32 &P, int64_t i, const double *,
                                       const double *) {
   const int c = P.cell[i];
   return (c >= 0 && c < I.N) ? c : -1;
 }
-__device__ __forceinline__ int key_of(const InstDev &I, const P64 &P, int64_t i, const double *nodes,
+__device__ __forceinline__ int key_of(CInst &I, const P64 &P, int64_t i, const double *nodes,
                                       const double *h) {
   const double x = P.x[i];
   if (!(x >= 0.0 && x < I.L)) return -1;
@@ -52,7 +52,7 @@ __device__ void seg_prefix_setup(const InstDev *insts, const InstState *states, 
                                  int *prefix) {
   const int nseg = 2 * n_inst;
   for (int s = threadIdx.x; s < nseg; s += blockDim.x) {
-    const InstDev &I = insts[s >> 1];
+    CInst &I = cinst(insts)[s >> 1];
     const InstState &S = states[s >> 1];
     const bool ok = I.active && S.frozen == 0 && (s & 1) < I.nsp;
     const int64_t ext = ok ? S.extent[s & 1] : 0;
@@ -66,13 +66,13 @@ __device__ void seg_prefix_setup(const InstDev *insts, const InstState *states, 
 }
 
 template <class P>
-__device__ __forceinline__ P make_view(const InstDev &I, int s, int buf);
+__device__ __forceinline__ P make_view(CInst &I, int s, int buf);
 template <>
-__device__ __forceinline__ P32 make_view<P32>(const InstDev &I, int s, int buf) {
+__device__ __forceinline__ P32 make_view<P32>(CInst &I, int s, int buf) {
   return view32(I.pbuf[s][buf], I.cap[s]);
 }
 template <>
-__device__ __forceinline__ P64 make_view<P64>(const InstDev &I, int s, int buf) {
+__device__ __forceinline__ P64 make_view<P64>(CInst &I, int s, int buf) {
   return view64(I.pbuf[s][buf], I.cap[s]);
 }
 
@@ -90,12 +90,12 @@ k_sort_count(const InstDev *__restrict__ insts, const InstState *__restrict__ st
   const int64_t T = sm.seg_prefix[nseg];
   const int64_t t0 = T * blockIdx.x / gridDim.x, t1 = T * (blockIdx.x + 1) / gridDim.x;
   int seg = -1;
-  const InstDev *Ip = nullptr;
+  CInst *Ip = nullptr;
   P view;
   int64_t ext = 0;
   auto flush = [&]() {
     __syncthreads();
-    const InstDev &I = *Ip;
+    CInst &I = *Ip;
     for (int j = threadIdx.x; j < I.N; j += kSB) {
       const unsigned int v = hist[j];
       if (v) {
@@ -112,7 +112,7 @@ k_sort_count(const InstDev *__restrict__ insts, const InstState *__restrict__ st
     if (s != seg) {
       if (seg >= 0) flush();
       seg = s;
-      Ip = &insts[seg >> 1];
+      Ip = &cinst(insts)[seg >> 1];
       const InstState &S = states[seg >> 1];
       ext = S.extent[seg & 1];
       view = make_view<P>(*Ip, seg & 1, S.parity);
@@ -135,7 +135,7 @@ k_sort_count(const InstDev *__restrict__ insts, const InstState *__restrict__ st
 __global__ void __launch_bounds__(kSB)
 k_sort_scan(const InstDev *__restrict__ insts, InstState *__restrict__ states) {
   __shared__ unsigned long long tmp[kSB];
-  const InstDev &I = insts[blockIdx.x];
+  CInst &I = cinst(insts)[blockIdx.x];
   InstState &S = states[blockIdx.x];
   if (!I.active || S.frozen != 0) return;
   const int N = I.N;
@@ -256,10 +256,10 @@ __device__ __forceinline__ void store_rec(const P64 &P, int64_t d, const Rec64 &
   gstore<int>(P.knext + d, r.knext);
   gstore<uint64_t>(P.id + d, r.id);
 }
-__device__ __forceinline__ int rec_key(const InstDev &I, const Rec32 &r, const double *) {
+__device__ __forceinline__ int rec_key(CInst &I, const Rec32 &r, const double *) {
   return (r.cell >= 0 && r.cell < I.N) ? r.cell : -1;
 }
-__device__ __forceinline__ int rec_key(const InstDev &I, const Rec64 &r, const double *nodes) {
+__device__ __forceinline__ int rec_key(CInst &I, const Rec64 &r, const double *nodes) {
   const double x = r.x;
   if (!(x >= 0.0 && x < I.L)) return -1;
   if (I.uniform) {
@@ -291,7 +291,7 @@ k_sort_scatter(const InstDev *__restrict__ insts, InstState *__restrict__ states
   const int64_t T = sm.seg_prefix[nseg];
   const int64_t t0 = T * blockIdx.x / gridDim.x, t1 = T * (blockIdx.x + 1) / gridDim.x;
   int seg = -1;
-  const InstDev *Ip = nullptr;
+  CInst *Ip = nullptr;
   P src, dst;
   int64_t ext = 0;
   for (int64_t tile = t0; tile < t1; ++tile) {
@@ -301,7 +301,7 @@ k_sort_scatter(const InstDev *__restrict__ insts, InstState *__restrict__ states
     if (s != seg) {
       __syncthreads();
       seg = s;
-      Ip = &insts[seg >> 1];
+      Ip = &cinst(insts)[seg >> 1];
       const InstState &S = states[seg >> 1];
       ext = S.extent[seg & 1];
       src = make_view<P>(*Ip, seg & 1, S.parity);
@@ -310,7 +310,7 @@ k_sort_scatter(const InstDev *__restrict__ insts, InstState *__restrict__ states
         for (int j = threadIdx.x; j <= Ip->N; j += kSB) sNodes[j] = Ip->nodes[j];
       __syncthreads();
     }
-    const InstDev &I = *Ip;
+    CInst &I = *Ip;
     const int64_t i0 = (tile - sm.seg_prefix[seg]) * kSTile + (int64_t)threadIdx.x * kSPPT;
     typename RecOf<P>::T r[kSPPT];
     bool ok[kSPPT];
@@ -345,7 +345,7 @@ k_sort_scatter(const InstDev *__restrict__ insts, InstState *__restrict__ states
 __global__ void __launch_bounds__(256)
 k_sort_finish(const InstDev *__restrict__ insts, InstState *__restrict__ states, int n_inst) {
   for (int i = threadIdx.x; i < n_inst; i += blockDim.x) {
-    const InstDev &I = insts[i];
+    CInst &I = cinst(insts)[i];
     InstState &S = states[i];
     if (!I.active || S.frozen != 0) continue;
     for (int s = 0; s < I.nsp; ++s) {
