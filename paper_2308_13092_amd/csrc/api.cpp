@@ -848,13 +848,17 @@ pic_status pic_get_state(pic_ctx *c, int32_t inst, int32_t species, pic_state_vi
     P32 P = view32(b, cap);
     std::vector<int32_t> cell(ext);
     std::vector<float> off(ext), vx(ext), vy(ext), vz(ext);
+    std::vector<Cold32> cold(ext);
     HIP_TRY(c, hipMemcpy(cell.data(), P.cell, 4 * ext, hipMemcpyDeviceToHost));
     HIP_TRY(c, hipMemcpy(off.data(), P.off, 4 * ext, hipMemcpyDeviceToHost));
     HIP_TRY(c, hipMemcpy(vx.data(), P.vx, 4 * ext, hipMemcpyDeviceToHost));
-    HIP_TRY(c, hipMemcpy(vy.data(), P.vy, 4 * ext, hipMemcpyDeviceToHost));
-    HIP_TRY(c, hipMemcpy(vz.data(), P.vz, 4 * ext, hipMemcpyDeviceToHost));
     HIP_TRY(c, hipMemcpy(kn.data(), P.knext, 4 * ext, hipMemcpyDeviceToHost));
-    HIP_TRY(c, hipMemcpy(id.data(), P.id, 8 * ext, hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(cold.data(), P.cold, sizeof(Cold32) * ext, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < ext; ++i) {
+      vy[i] = cold[i].vy;
+      vz[i] = cold[i].vz;
+      id[i] = cold[i].id;
+    }
     for (int64_t i = 0; i < ext; ++i) live += cell[i] >= 0;
     if (live > v->n) { v->n = live; return fail(c, PIC_EINVAL, "view too small"); }
     int64_t o = 0;
@@ -933,10 +937,11 @@ pic_status pic_set_state(pic_ctx *c, int32_t inst, int32_t species, const pic_st
       HIP_TRY(c, hipMemcpy(P.cell, v->cell, 4 * n, hipMemcpyHostToDevice));
       HIP_TRY(c, hipMemcpy(P.off, v->off, 4 * n, hipMemcpyHostToDevice));
       HIP_TRY(c, hipMemcpy(P.vx, v->vx, 4 * n, hipMemcpyHostToDevice));
-      HIP_TRY(c, hipMemcpy(P.vy, v->vy, 4 * n, hipMemcpyHostToDevice));
-      HIP_TRY(c, hipMemcpy(P.vz, v->vz, 4 * n, hipMemcpyHostToDevice));
       HIP_TRY(c, hipMemcpy(P.knext, v->knext, 4 * n, hipMemcpyHostToDevice));
-      HIP_TRY(c, hipMemcpy(P.id, v->id, 8 * n, hipMemcpyHostToDevice));
+      std::vector<Cold32> cold(n);
+      for (int64_t i = 0; i < n; ++i)
+        cold[i] = Cold32{((const float *)v->vy)[i], ((const float *)v->vz)[i], v->id[i]};
+      HIP_TRY(c, hipMemcpy(P.cold, cold.data(), sizeof(Cold32) * n, hipMemcpyHostToDevice));
     } else {
       P64 P = view64(b, cap);
       HIP_TRY(c, hipMemcpy(P.x, v->x, 8 * n, hipMemcpyHostToDevice));

@@ -9,8 +9,10 @@
 // Particles are stored as structure-of-arrays, each field a contiguous array
 // of `cap` elements (cap is a multiple of 64, so every array is 256-B
 // aligned):
-//   FP32-state form: cell i32 | off f32 | vx f32 | vy f32 | vz f32 | knext i32 | id u64
+//   FP32-state form: cell i32 | off f32 | vx f32 | knext i32 | {vy f32, vz f32, id u64}
 //   FP64 form:       x f64    | vx f64  | vy f64 | vz f64 | knext i32 | id u64
+// (the FP32 form keeps the fields the streaming pass never reads in one 16-B
+// record per particle).
 // A dead (absorbed) particle keeps its slot until the next sort with
 // cell = -1 (FP32) or x = -1 (FP64).
 #pragma once
@@ -115,8 +117,16 @@ struct InstState {
 // ---------------------------------------------------------------------------
 // Particle buffer views
 // ---------------------------------------------------------------------------
+// FP32 form: the fields every step streams (cell, off, vx, knext) are
+// separate arrays; the ones only collisions, emission, diagnostics and the
+// sort touch (vy, vz, id) form one 16-B record per particle, so that handling
+// a single particle costs one memory line for them instead of three.
+struct Cold32 {
+  float vy, vz;
+  uint64_t id;
+};
 struct P32 {
-  int32_t *cell; float *off, *vx, *vy, *vz; int32_t *knext; uint64_t *id;
+  int32_t *cell; float *off, *vx; int32_t *knext; Cold32 *cold;
 };
 struct P64 {
   double *x, *vx, *vy, *vz; int32_t *knext; uint64_t *id;
@@ -126,10 +136,8 @@ __host__ __device__ inline P32 view32(char *b, int64_t cap) {
   p.cell = reinterpret_cast<int32_t *>(b);
   p.off = reinterpret_cast<float *>(b + 4 * cap);
   p.vx = reinterpret_cast<float *>(b + 8 * cap);
-  p.vy = reinterpret_cast<float *>(b + 12 * cap);
-  p.vz = reinterpret_cast<float *>(b + 16 * cap);
-  p.knext = reinterpret_cast<int32_t *>(b + 20 * cap);
-  p.id = reinterpret_cast<uint64_t *>(b + 24 * cap);
+  p.knext = reinterpret_cast<int32_t *>(b + 12 * cap);
+  p.cold = reinterpret_cast<Cold32 *>(b + 16 * cap);   // cap is a multiple of 64
   return p;
 }
 __host__ __device__ inline P64 view64(char *b, int64_t cap) {
@@ -175,6 +183,17 @@ __device__ __forceinline__ double2 gload2(const double *p) {
 }
 __device__ __forceinline__ void gstore4(int *p, int a, int b, int c, int d) {
   ecpic_iv4 v = {a, b, c, d};
+  *(ECPIC_GLOBAL ecpic_iv4 *)p = v;
+}
+// One particle's cold record as one 16-B load / store.
+__device__ __forceinline__ Cold32 gload_cold(const Cold32 *p) {
+  const ecpic_iv4 v = *(const ECPIC_GLOBAL ecpic_iv4 *)p;
+  return Cold32{__int_as_float(v.x), __int_as_float(v.y),
+                (uint64_t)(uint32_t)v.z | ((uint64_t)(uint32_t)v.w << 32)};
+}
+__device__ __forceinline__ void gstore_cold(Cold32 *p, const Cold32 &c) {
+  ecpic_iv4 v = {__float_as_int(c.vy), __float_as_int(c.vz), (int)(uint32_t)c.id,
+                 (int)(uint32_t)(c.id >> 32)};
   *(ECPIC_GLOBAL ecpic_iv4 *)p = v;
 }
 __device__ __forceinline__ void gstore4(float *p, float a, float b, float c, float d) {

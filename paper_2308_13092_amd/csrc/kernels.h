@@ -10,7 +10,7 @@ enum Mode : int { M_DEPOSIT = 0, M_PUSH = 1, M_MCC = 2, M_FUSED = 3, M_PULLBACK 
 
 // Dynamic LDS bytes of the particle kernels for grids of up to max_n cells.
 size_t particle_lds_bytes(int prec, int max_n, int block);
-size_t sort_lds_bytes(int max_n);
+size_t sort_lds_bytes(int max_n, int prec);
 
 void launch_field(const InstDev *insts, InstState *states, int n_inst, int mode, hipStream_t s);
 void launch_init(const InstDev *insts, InstState *states, int inst, int species, int prec,

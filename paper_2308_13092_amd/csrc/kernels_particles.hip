@@ -412,16 +412,15 @@ __device__ void write_new(CInst &I, typename F::View P, int64_t idx, double x, i
     P.cell[idx] = cell;
     P.off[idx] = off;
     P.vx[idx] = (float)vx;
-    P.vy[idx] = (float)vy;
-    P.vz[idx] = (float)vz;
+    gstore_cold(P.cold + idx, Cold32{(float)vy, (float)vz, id});
   } else {
     P.x[idx] = x;
     P.vx[idx] = vx;
     P.vy[idx] = vy;
     P.vz[idx] = vz;
+    P.id[idx] = id;
   }
   P.knext[idx] = kn;
-  P.id[idx] = id;
 }
 
 // Secondary emission by an ion absorbed at `wall` during step k.  The new
@@ -479,7 +478,9 @@ __device__ void emit_secondary(CInst &I, InstState &S, Smem &sm, uint64_t ion_id
 // ---------------------------------------------------------------------------
 // Queue entry: particle index | kind << 30; kind 0 = collision candidate,
 // 1 / 2 = absorbed at the left / right electrode, 3 = non-finite state.
-constexpr int kWaveQ = 320;   // per-wavefront LDS queue: 63 carried + 256 new entries fit
+constexpr int kSpill = 256;   // entries moved to HBM per reservation
+constexpr int kWaveQ = 320;   // per-wavefront LDS queue: kSpill - 1 carried + 64 new entries fit
+static_assert(kSpill - 1 + 64 <= kWaveQ, "wavefront queue too small");
 constexpr int kQShift = 30;
 constexpr int kQMask = (1 << kQShift) - 1;
 __device__ __forceinline__ int qentry(int i, int kind) { return i | (kind << kQShift); }
@@ -573,22 +574,24 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
   float qmdt32 = 0.0f, hq32 = 0.0f;
   double qmdt = 0.0, hq = 0.0, dt = 0.0, L = 0.0;
 
-  // Append this lane's entry (if any) to the wavefront queue; move full
-  // groups of 64 (or, at the end of a segment, all) to the segment's HBM queue.
+  // Append this lane's entry (if any) to the wavefront queue; move whole
+  // chunks of kSpill entries (or, at the end of a segment, all) to the
+  // segment's HBM queue.  The reservation is an atomic on the segment's one
+  // counter, which every wavefront of the device shares: chunks keep those
+  // same-address atomics (which serialise) few.
   auto enqueue = [&](bool want, int entry) {
     const unsigned long long m = __ballot(want);
     if (want) wq[wq_n + __popcll(m & lt_mask)] = entry;
     wq_n += __popcll(m);
   };
   auto spill = [&](bool all) {
-    while (wq_n >= 64 || (all && wq_n > 0)) {
-      const int n = wq_n < 64 ? wq_n : 64;
-      unsigned long long b = 0;
-      if (lane == 0) b = atomicAdd(&Sp->qcount[sp], (unsigned long long)n);
-      b = __shfl(b, 0, 64);
-      if (lane < n) gstore<int>(gq + b + lane, wq[wq_n - n + lane]);
-      wq_n -= n;
-    }
+    const int n = all ? wq_n : (wq_n / kSpill) * kSpill;
+    if (n == 0) return;
+    unsigned long long b = 0;
+    if (lane == 0) b = atomicAdd(&Sp->qcount[sp], (unsigned long long)n);
+    b = __shfl(b, 0, 64);
+    for (int e = lane; e < n; e += 64) gstore<int>(gq + b + e, wq[wq_n - n + e]);
+    wq_n -= n;
   };
   auto flush = [&]() {
     spill(true);
@@ -776,7 +779,7 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
               const double x = I.uniform ? ((double)jj * I.dx + (double)sig * I.dx)
                                          : (I.nodes[jj] + (double)sig * I.h[jj]);
               if (fabs(x - I.eedf_centre) < I.eedf_half)
-                eedf_sample(I, x, (double)v1, (double)P.vy[ii], (double)P.vz[ii]);
+                eedf_sample(I, x, (double)v1, (double)P.cold[ii].vy, (double)P.cold[ii].vz);
             }
             if constexpr (MODE == M_FUSED) {
               int64_t w0, w1;
@@ -944,11 +947,30 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
     }
     if constexpr (MODE == M_PUSH || MODE == M_MCC || MODE == M_FUSED) {
 #pragma unroll
-      for (int q = 0; q < kPPT; ++q) enqueue(want[q], went[q]);
-      spill(false);
+      for (int q = 0; q < kPPT; ++q) {
+        enqueue(want[q], went[q]);   // at most 64 more: kSpill - 1 + 64 <= kWaveQ
+        spill(false);
+      }
     }
   }
   if (seg >= 0) flush();
+}
+
+// Velocity and id of particle i.
+__device__ __forceinline__ void load_particle(const P32 &P, int64_t i, double &vx, double &vy,
+                                              double &vz, uint64_t &id) {
+  const Cold32 c = gload_cold(P.cold + i);
+  vx = (double)gload<float>(P.vx + i);
+  vy = (double)c.vy;
+  vz = (double)c.vz;
+  id = c.id;
+}
+__device__ __forceinline__ void load_particle(const P64 &P, int64_t i, double &vx, double &vy,
+                                              double &vz, uint64_t &id) {
+  vx = P.vx[i];
+  vy = P.vy[i];
+  vz = P.vz[i];
+  id = P.id[i];
 }
 
 // Handle one queued particle: absorption (tallies, secondary emission) or a
@@ -964,18 +986,19 @@ __device__ void drain_one(CInst &I, InstState &S, Smem &sm, int sp, int buf, int
     atomicAdd(&sm.ctr[C_NONFINITE], 1ull);
     return;
   }
-  const double vxd = (double)P.vx[i], vy = (double)P.vy[i], vz = (double)P.vz[i];
+  double vxd, vy, vz;
+  uint64_t id;
+  load_particle(P, i, vxd, vy, vz, id);
   if (kind != 0) {
     const int wi = kind - 1;
     atomicAdd(&sm.ctr[C_ABS + 2 * sp + wi], 1ull);
     const double en = (0.5 * I.mass[sp] / kQE) * ((vxd * vxd + vy * vy) + vz * vz);
     atomicAdd(&sm.ctr[C_EABS + 2 * sp + wi], (unsigned long long)rint(en * 65536.0));
     if (sp == 1 && I.gamma_see > 0.0 && I.nsp > 1)
-      emit_secondary<F>(I, S, sm, P.id[i], wi == 0 ? -1 : 1, k, buf, MODE == M_FUSED,
+      emit_secondary<F>(I, S, sm, id, wi == 0 ? -1 : 1, k, buf, MODE == M_FUSED,
                         I.A[(k + 1) & 1][0]);
     return;
   }
-  const uint64_t id = P.id[i];
   double ux = vxd, uy = vy, uz = vz;
   bool bound = false;
   atomicAdd(&sm.ctr[C_CAND + sp], 1ull);
@@ -1028,8 +1051,7 @@ __device__ void drain_one(CInst &I, InstState &S, Smem &sm, int sp, int buf, int
   if (bound) atomicAdd(&sm.ctr[C_BOUND], 1ull);
   if constexpr (F::prec == 1) {
     P.vx[i] = (float)ux;
-    P.vy[i] = (float)uy;
-    P.vz[i] = (float)uz;
+    gstore_cold(P.cold + i, Cold32{(float)uy, (float)uz, id});
   } else {
     P.vx[i] = ux;
     P.vy[i] = uy;
@@ -1165,7 +1187,7 @@ k_diag(const InstDev *__restrict__ insts, const InstState *__restrict__ states, 
       double vx, vy, vz;
       if constexpr (F::prec == 1) {
         if (P.cell[i] < 0) continue;
-        vx = P.vx[i]; vy = P.vy[i]; vz = P.vz[i];
+        vx = P.vx[i]; vy = P.cold[i].vy; vz = P.cold[i].vz;
       } else {
         if (!(P.x[i] >= 0.0)) continue;
         vx = P.vx[i]; vy = P.vy[i]; vz = P.vz[i];

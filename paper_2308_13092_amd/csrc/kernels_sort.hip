@@ -47,16 +47,35 @@ __device__ __forceinline__ int key_of(CInst &I, const P64 &P, int64_t i, const d
   return lo;
 }
 
+// Runs of equal keys in consecutive lanes of a wavefront (particles arrive
+// nearly sorted by cell, so a wavefront holds few runs).  Returns whether this
+// lane starts its run; len is the run's length and pos this lane's place in
+// it.  Letting only the first lane of a run update a counter avoids the
+// serialisation of many lanes updating one LDS address.
+__device__ __forceinline__ bool key_run(int key, int &len, int &pos) {
+  const int lane = __lane_id();
+  const int prev = __shfl_up(key, 1, 64);
+  const bool head = lane == 0 || key != prev;
+  const unsigned long long heads = __ballot(head);
+  const unsigned long long le = (2ull << lane) - 1ull;   // lanes 0..lane (all for lane 63)
+  const int h = 63 - __clzll((long long)(heads & le));
+  const unsigned long long above = heads & ~le;
+  const int nxt = above ? __ffsll((long long)above) - 1 : 64;
+  pos = lane - h;
+  len = nxt - h;
+  return head;
+}
+
 // Segment tile prefix over the instances that are not frozen.
 __device__ void seg_prefix_setup(const InstDev *insts, const InstState *states, int n_inst,
-                                 int *prefix) {
+                                 int *prefix, int tile = kSTile) {
   const int nseg = 2 * n_inst;
   for (int s = threadIdx.x; s < nseg; s += blockDim.x) {
     CInst &I = cinst(insts)[s >> 1];
     const InstState &S = states[s >> 1];
     const bool ok = I.active && S.frozen == 0 && (s & 1) < I.nsp;
     const int64_t ext = ok ? S.extent[s & 1] : 0;
-    prefix[s + 1] = (int)((ext + kSTile - 1) / kSTile);
+    prefix[s + 1] = (int)((ext + tile - 1) / tile);
   }
   if (threadIdx.x == 0) prefix[0] = 0;
   __syncthreads();
@@ -76,6 +95,27 @@ __device__ __forceinline__ P64 make_view<P64>(CInst &I, int s, int buf) {
   return view64(I.pbuf[s][buf], I.cap[s]);
 }
 
+constexpr int kCTile = kSB * 16;   // particles per tile of the count kernel
+
+// Cell keys of particles i0..i0+3 (-1: dead or beyond the extent).
+__device__ __forceinline__ void count_keys(CInst &I, const P32 &P, int64_t i0, int64_t ext,
+                                           const double *, int *key) {
+  if (i0 + 4 <= ext) {
+    const int4 c = gload4(P.cell + i0);
+    const int cc[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) key[q] = (cc[q] >= 0 && cc[q] < I.N) ? cc[q] : -1;
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) key[q] = (i0 + q < ext) ? key_of(I, P, i0 + q, nullptr, nullptr) : -1;
+  }
+}
+__device__ __forceinline__ void count_keys(CInst &I, const P64 &P, int64_t i0, int64_t ext,
+                                           const double *nodes, int *key) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) key[q] = (i0 + q < ext) ? key_of(I, P, i0 + q, nodes, nullptr) : -1;
+}
+
 template <class P>
 __global__ void __launch_bounds__(kSB)
 k_sort_count(const InstDev *__restrict__ insts, const InstState *__restrict__ states, int n_inst,
@@ -85,7 +125,7 @@ k_sort_count(const InstDev *__restrict__ insts, const InstState *__restrict__ st
   unsigned int *hist = reinterpret_cast<unsigned int *>(dsm);
   double *sNodes = reinterpret_cast<double *>(dsm + 4 * ((max_n + 2) & ~1));
   for (int j = threadIdx.x; j < max_n; j += kSB) hist[j] = 0;
-  seg_prefix_setup(insts, states, n_inst, sm.seg_prefix);
+  seg_prefix_setup(insts, states, n_inst, sm.seg_prefix, kCTile);
   const int nseg = 2 * n_inst;
   const int64_t T = sm.seg_prefix[nseg];
   const int64_t t0 = T * blockIdx.x / gridDim.x, t1 = T * (blockIdx.x + 1) / gridDim.x;
@@ -116,16 +156,23 @@ k_sort_count(const InstDev *__restrict__ insts, const InstState *__restrict__ st
       const InstState &S = states[seg >> 1];
       ext = S.extent[seg & 1];
       view = make_view<P>(*Ip, seg & 1, S.parity);
-      if (!Ip->uniform)
+      if (sizeof(P) == sizeof(P64) && !Ip->uniform)
         for (int j = threadIdx.x; j <= Ip->N; j += kSB) sNodes[j] = Ip->nodes[j];
       __syncthreads();
     }
-    const int64_t i0 = (tile - sm.seg_prefix[seg]) * kSTile + (int64_t)threadIdx.x * kSPPT;
-    for (int q = 0; q < kSPPT; ++q) {
-      const int64_t i = i0 + q;
-      if (i >= ext) break;
-      const int key = key_of(*Ip, view, i, sNodes, nullptr);
-      if (key >= 0) atomicAdd(&hist[key], 1u);
+    // The thread's particles: 4 groups of 4 consecutive ones, each group
+    // read by one vector load that is contiguous across the wavefront.
+    const int64_t base = (tile - sm.seg_prefix[seg]) * kCTile;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int64_t i0 = base + 4 * ((int64_t)g * kSB + threadIdx.x);
+      int key[4];
+      count_keys(*Ip, view, i0, ext, sNodes, key);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        int len, pos;
+        if (key_run(key[q], len, pos) && key[q] >= 0) atomicAdd(&hist[key[q]], (unsigned int)len);
+      }
     }
   }
   if (seg >= 0) flush();
@@ -176,27 +223,22 @@ template <class P> struct RecOf;
 template <> struct RecOf<P32> { using T = Rec32; };
 template <> struct RecOf<P64> { using T = Rec64; };
 
-// Load the 4 consecutive particles of a thread (vector loads when all four
-// are inside the extent).
+// Load the 4 consecutive particles i0..i0+3 of a thread (vector loads when
+// all four are inside the extent).
 __device__ __forceinline__ void load_recs(const P32 &P, int64_t i0, int64_t ext, Rec32 *r, bool *ok) {
   if (i0 + 4 <= ext) {
     const int4 c = gload4(P.cell + i0);
-    const float4 o = gload4(P.off + i0), x = gload4(P.vx + i0), y = gload4(P.vy + i0),
-                 z = gload4(P.vz + i0);
+    const float4 o = gload4(P.off + i0), x = gload4(P.vx + i0);
     const int4 k = gload4(P.knext + i0);
-    const ecpic_iv4 ia = *(const ECPIC_GLOBAL ecpic_iv4 *)(P.id + i0);
-    const ecpic_iv4 ib = *(const ECPIC_GLOBAL ecpic_iv4 *)(P.id + i0 + 2);
+    Cold32 cd[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) cd[q] = gload_cold(P.cold + i0 + q);
     const int cc[4] = {c.x, c.y, c.z, c.w};
-    const float oo[4] = {o.x, o.y, o.z, o.w}, xx[4] = {x.x, x.y, x.z, x.w},
-                yy[4] = {y.x, y.y, y.z, y.w}, zz[4] = {z.x, z.y, z.z, z.w};
+    const float oo[4] = {o.x, o.y, o.z, o.w}, xx[4] = {x.x, x.y, x.z, x.w};
     const int kk[4] = {k.x, k.y, k.z, k.w};
-    const uint64_t ii[4] = {(uint64_t)(uint32_t)ia.x | ((uint64_t)(uint32_t)ia.y << 32),
-                            (uint64_t)(uint32_t)ia.z | ((uint64_t)(uint32_t)ia.w << 32),
-                            (uint64_t)(uint32_t)ib.x | ((uint64_t)(uint32_t)ib.y << 32),
-                            (uint64_t)(uint32_t)ib.z | ((uint64_t)(uint32_t)ib.w << 32)};
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      r[q] = Rec32{cc[q], oo[q], xx[q], yy[q], zz[q], kk[q], ii[q]};
+      r[q] = Rec32{cc[q], oo[q], xx[q], cd[q].vy, cd[q].vz, kk[q], cd[q].id};
       ok[q] = true;
     }
   } else {
@@ -204,8 +246,10 @@ __device__ __forceinline__ void load_recs(const P32 &P, int64_t i0, int64_t ext,
     for (int q = 0; q < 4; ++q) {
       const int64_t i = i0 + q;
       ok[q] = i < ext;
-      if (ok[q])
-        r[q] = Rec32{P.cell[i], P.off[i], P.vx[i], P.vy[i], P.vz[i], P.knext[i], P.id[i]};
+      if (ok[q]) {
+        const Cold32 cd = gload_cold(P.cold + i);
+        r[q] = Rec32{P.cell[i], P.off[i], P.vx[i], cd.vy, cd.vz, P.knext[i], cd.id};
+      }
     }
   }
 }
@@ -239,14 +283,13 @@ __device__ __forceinline__ void load_recs(const P64 &P, int64_t i0, int64_t ext,
     }
   }
 }
+
 __device__ __forceinline__ void store_rec(const P32 &P, int64_t d, const Rec32 &r) {
   gstore<int>(P.cell + d, r.cell);
   gstore<float>(P.off + d, r.off);
   gstore<float>(P.vx + d, r.vx);
-  gstore<float>(P.vy + d, r.vy);
-  gstore<float>(P.vz + d, r.vz);
   gstore<int>(P.knext + d, r.knext);
-  gstore<uint64_t>(P.id + d, r.id);
+  gstore_cold(P.cold + d, Cold32{r.vy, r.vz, r.id});
 }
 __device__ __forceinline__ void store_rec(const P64 &P, int64_t d, const Rec64 &r) {
   gstore<double>(P.x + d, r.x);
@@ -281,10 +324,11 @@ k_sort_scatter(const InstDev *__restrict__ insts, InstState *__restrict__ states
                int max_n, unsigned int *__restrict__ done) {
   __shared__ SortSmem sm;
   extern __shared__ __align__(16) unsigned char dsm[];
+  // LDS: per-cell counts u32, per-cell destination bases u64 and, FP64
+  // only, the node positions to locate x.
   unsigned int *cnt = reinterpret_cast<unsigned int *>(dsm);
-  double *sNodes = reinterpret_cast<double *>(dsm + 4 * ((max_n + 2) & ~1));
-  unsigned long long *gbase =
-      reinterpret_cast<unsigned long long *>(sNodes + (max_n + 1));
+  unsigned long long *gbase = reinterpret_cast<unsigned long long *>(dsm + 4 * ((max_n + 2) & ~1));
+  double *sNodes = reinterpret_cast<double *>(gbase + max_n);
   for (int j = threadIdx.x; j < max_n; j += kSB) cnt[j] = 0;
   seg_prefix_setup(insts, states, n_inst, sm.seg_prefix);
   const int nseg = 2 * n_inst;
@@ -306,7 +350,7 @@ k_sort_scatter(const InstDev *__restrict__ insts, InstState *__restrict__ states
       ext = S.extent[seg & 1];
       src = make_view<P>(*Ip, seg & 1, S.parity);
       dst = make_view<P>(*Ip, seg & 1, S.parity ^ 1);
-      if (!Ip->uniform)
+      if (sizeof(P) == sizeof(P64) && !Ip->uniform)
         for (int j = threadIdx.x; j <= Ip->N; j += kSB) sNodes[j] = Ip->nodes[j];
       __syncthreads();
     }
@@ -317,12 +361,18 @@ k_sort_scatter(const InstDev *__restrict__ insts, InstState *__restrict__ states
     load_recs(src, i0, ext, r, ok);
     int key[kSPPT];
     unsigned int rank[kSPPT];
-    // Rank of each particle among the tile's particles of its cell (LDS
-    // atomics; the order within a cell is not defined).
+    // Rank of each particle among the tile's particles of its cell: one LDS
+    // atomic per run of equal cells across the lanes (for a given q the
+    // lanes hold particles 4 apart, still in nearly sorted order; the order
+    // within a cell is not defined).
 #pragma unroll
     for (int q = 0; q < kSPPT; ++q) {
       key[q] = ok[q] ? rec_key(I, r[q], sNodes) : -1;
-      rank[q] = (key[q] >= 0) ? atomicAdd(&cnt[key[q]], 1u) : 0u;
+      int len, pos;
+      unsigned int b0 = 0;
+      if (key_run(key[q], len, pos) && key[q] >= 0) b0 = atomicAdd(&cnt[key[q]], (unsigned int)len);
+      b0 = __shfl(b0, __lane_id() - pos, 64);
+      rank[q] = b0 + (unsigned int)pos;
     }
     __syncthreads();
     // The first particle of each cell in the tile reserves the tile's range.
@@ -356,17 +406,19 @@ k_sort_finish(const InstDev *__restrict__ insts, InstState *__restrict__ states,
   }
 }
 
-size_t sort_lds_bytes(int max_n) {
-  return 4 * (size_t)((max_n + 2) & ~1) + 8 * (size_t)(max_n + 1) + 8 * (size_t)max_n;
+size_t sort_lds_bytes(int max_n, int prec) {
+  return 4 * (size_t)((max_n + 2) & ~1) + 8 * (size_t)max_n + (prec == 0 ? 8 * (size_t)(max_n + 1) : 0);
 }
 
 hipError_t launch_sort(const InstDev *insts, InstState *states, int n_inst, int prec, int grid,
                        int max_n, unsigned int *done, hipStream_t s) {
-  const size_t lds = sort_lds_bytes(max_n);
+  const size_t lds = sort_lds_bytes(max_n, prec);
+  // The count needs only the histogram (and, FP64, the nodes to locate x).
+  const size_t lds_count = 4 * (size_t)((max_n + 2) & ~1) + (prec == 0 ? 8 * (size_t)(max_n + 1) : 0);
   if (prec == 1)
-    hipLaunchKernelGGL(k_sort_count<P32>, dim3(grid), dim3(kSB), lds, s, insts, states, n_inst, max_n);
+    hipLaunchKernelGGL(k_sort_count<P32>, dim3(grid), dim3(kSB), lds_count, s, insts, states, n_inst, max_n);
   else
-    hipLaunchKernelGGL(k_sort_count<P64>, dim3(grid), dim3(kSB), lds, s, insts, states, n_inst, max_n);
+    hipLaunchKernelGGL(k_sort_count<P64>, dim3(grid), dim3(kSB), lds_count, s, insts, states, n_inst, max_n);
   hipLaunchKernelGGL(k_sort_scan, dim3(n_inst), dim3(kSB), 0, s, insts, states);
   if (prec == 1)
     hipLaunchKernelGGL(k_sort_scatter<P32>, dim3(grid), dim3(kSB), lds, s, insts, states, n_inst, max_n, done);
