@@ -154,7 +154,7 @@ typedef struct pic_state_view {
 
 /* Launch tuning (chosen by the autotuner, or set by hand). */
 typedef struct pic_tuning {
-  int32_t block;          /* threads per block of the fused particle kernel: 256, 512, 1024 */
+  int32_t block;          /* threads per block of the fused particle kernel: 256, 512, 1024 (default 1024) */
   int32_t blocks_per_cu;  /* persistent particle-kernel blocks per compute unit (1-16;
                              0 = as many as the CU's LDS holds at once, at most 8)     */
   int32_t sort_interval;  /* steps between cell sorts (0 = never)                     */

@@ -211,7 +211,7 @@ struct pic_ctx {
   unsigned int *d_done = nullptr;   // [0] particles, [1] sort
   unsigned long long *d_diag = nullptr;
   int max_n = 2;
-  pic_tuning tune{512, 0, 0, 1};
+  pic_tuning tune{1024, 0, 0, 1};   // 1024 threads per block: measured fastest on the large workload
   int64_t host_step = 0;
   bool deposit_current = false;
   std::string err;

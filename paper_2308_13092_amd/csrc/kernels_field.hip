@@ -16,51 +16,74 @@
 
 namespace ecpic {
 
-constexpr int kFB = 256;  // threads per field workgroup
+constexpr int kFB = 1024;           // threads per field workgroup
+constexpr int kFW = kFB / 64;       // its wavefronts
 
 template <typename T>
+__device__ __forceinline__ T wave_scan_inclusive(T v) {
+  const int lane = __lane_id();
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const T u = __shfl_up(v, off, 64);
+    if (lane >= off) v += u;
+  }
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// In-place inclusive prefix sum of a[0..n) by the workgroup: each thread sums
+// a contiguous chunk, the chunk totals are scanned within each wavefront with
+// shuffles, then across the wavefronts; the blocking is fixed, so the result
+// is reproducible.  tmp holds kFW values.
+template <typename T>
 __device__ void block_scan_inclusive(T *a, int n, T *tmp) {
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int c = (n + kFB - 1) / kFB;
   const int lo = min(n, t * c), hi = min(n, lo + c);
   T s = T(0);
   for (int i = lo; i < hi; ++i) { s += a[i]; a[i] = s; }
-  tmp[t] = s;
+  const T incl = wave_scan_inclusive(s);
+  if (lane == 63) tmp[w] = incl;
   __syncthreads();
-  for (int off = 1; off < kFB; off <<= 1) {
-    const T v = (t >= off) ? tmp[t - off] : T(0);
-    __syncthreads();
-    tmp[t] += v;
-    __syncthreads();
+  if (w == 0) {
+    T x = (lane < kFW) ? tmp[lane] : T(0);
+    x = wave_scan_inclusive(x);
+    if (lane < kFW) tmp[lane] = x;
   }
-  const T base = (t > 0) ? tmp[t - 1] : T(0);
+  __syncthreads();
+  const T base = (incl - s) + ((w > 0) ? tmp[w - 1] : T(0));
   for (int i = lo; i < hi; ++i) a[i] += base;
   __syncthreads();
 }
 
 template <typename T>
 __device__ T block_sum(T v, T *tmp) {
-  const int t = threadIdx.x;
-  tmp[t] = v;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  v = wave_sum(v);
+  if (lane == 0) tmp[w] = v;
   __syncthreads();
-  for (int off = kFB / 2; off > 0; off >>= 1) {
-    if (t < off) tmp[t] += tmp[t + off];
-    __syncthreads();
-  }
-  const T r = tmp[0];
+  T r = T(0);
+#pragma unroll
+  for (int i = 0; i < kFW; ++i) r += tmp[i];
   __syncthreads();
   return r;
 }
 
 __device__ double block_max(double v, double *tmp) {
-  const int t = threadIdx.x;
-  tmp[t] = v;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  if (lane == 0) tmp[w] = v;
   __syncthreads();
-  for (int off = kFB / 2; off > 0; off >>= 1) {
-    if (t < off) tmp[t] = fmax(tmp[t], tmp[t + off]);
-    __syncthreads();
-  }
-  const double r = tmp[0];
+  double r = 0.0;
+#pragma unroll
+  for (int i = 0; i < kFW; ++i) r = fmax(r, tmp[i]);
   __syncthreads();
   return r;
 }
@@ -74,8 +97,9 @@ k_field(const InstDev *__restrict__ insts, InstState *__restrict__ states, int m
   __shared__ double sE[kMaxCells + 1];
   __shared__ double sQ[kMaxCells + 1];
   __shared__ int64_t sD[kMaxCells + 1];
-  __shared__ int64_t tmpi[kFB];
-  __shared__ double tmpd[kFB];
+  __shared__ double sH[kMaxCells + 1];
+  __shared__ int64_t tmpi[kFW];
+  __shared__ double tmpd[kFW];
 
   CInst &I = cinst(insts)[blockIdx.x];
   InstState &S = states[blockIdx.x];
@@ -91,6 +115,7 @@ k_field(const InstDev *__restrict__ insts, InstState *__restrict__ states, int m
   for (int n = t; n <= N; n += kFB) {
     sA[0][n] = I.A[par][0][n];
     sA[1][n] = (nsp > 1) ? I.A[par][1][n] : 0;
+    if (n < N) sH[n] = I.h[n];
   }
   __syncthreads();
   // Q_n = sum_s (q_s W A_{s,n}) 2^-32.
@@ -129,14 +154,14 @@ k_field(const InstDev *__restrict__ insts, InstState *__restrict__ states, int m
 
   // E_0 from sum_j h_j E_j = phi_0 - phi_N.
   double part = 0.0;
-  for (int j = t; j < N; j += kFB) part += I.h[j] * sG[j];
+  for (int j = t; j < N; j += kFB) part += sH[j] * sG[j];
   const double hg = block_sum<double>(part, tmpd);
   const double e0 = (phi0 - phiN - hg) / I.L;
   for (int j = t; j < N; j += kFB) sE[j] = e0 + sG[j];
   __syncthreads();
 
   // phi_j = phi_0 - sum_{i<j} h_i E_i  (reuse sG for the prefix).
-  for (int j = t; j < N; j += kFB) sG[j] = I.h[j] * sE[j];
+  for (int j = t; j < N; j += kFB) sG[j] = sH[j] * sE[j];
   __syncthreads();
   block_scan_inclusive<double>(sG, N, tmpd);
   for (int n = t; n <= N; n += kFB) {
@@ -157,9 +182,9 @@ k_field(const InstDev *__restrict__ insts, InstState *__restrict__ states, int m
     for (int n = t; n <= N; n += kFB) {
       double en;
       if (n > 0 && n < N) {
-        en = (I.h[n - 1] * sE[n - 1] + I.h[n] * sE[n]) / (I.h[n - 1] + I.h[n]);
+        en = (sH[n - 1] * sE[n - 1] + sH[n] * sE[n]) / (sH[n - 1] + sH[n]);
       } else if (periodic) {
-        en = (I.h[N - 1] * sE[N - 1] + I.h[0] * sE[0]) / (I.h[N - 1] + I.h[0]);
+        en = (sH[N - 1] * sE[N - 1] + sH[0] * sE[0]) / (sH[N - 1] + sH[0]);
       } else if (n == 0) {
         en = sE[0] - sQ[0] / kEPS0;
       } else {
@@ -172,7 +197,7 @@ k_field(const InstDev *__restrict__ insts, InstState *__restrict__ states, int m
 
   // Field energy and the density maximum (stability monitor 1b).
   double fe = 0.0;
-  for (int j = t; j < N; j += kFB) fe += I.h[j] * sE[j] * sE[j];
+  for (int j = t; j < N; j += kFB) fe += sH[j] * sE[j] * sE[j];
   fe = block_sum<double>(fe, tmpd);
   double nm = 0.0;
   for (int n = t; n <= N; n += kFB) nm = fmax(nm, ((double)sA[0][n] * I.W * 0x1p-32) / I.V[n]);

@@ -33,7 +33,8 @@ namespace ecpic {
 constexpr double kHALF_ME_OVER_QE = (0.5 * kME) / kQE;
 constexpr double kTWO_QE_OVER_ME = (2.0 * kQE) / kME;
 constexpr double kTWO_ME_OVER_M = (2.0 * kME) / kMAR;
-constexpr int kPPT = 4;                     // particles per thread per tile
+constexpr int kPPT = 4;                     // particles per thread per tile (a multiple of 4)
+static_assert(kPPT % 4 == 0, "vector loads move 4 particles");
 constexpr float kWalkLimit = 4194304.0f;    // |sigma| beyond 2^22 cells: out of any grid
 
 // ---------------------------------------------------------------------------
@@ -136,7 +137,7 @@ __device__ __forceinline__ void weights32(float off, int64_t &w0, int64_t &w1) {
 // its end and across into the next cell.  Almost every particle is done after
 // the first step, which needs no data beyond the entry already read for it.
 // ---------------------------------------------------------------------------
-enum : int { W_IN = 0, W_LEFT = -1, W_RIGHT = 1, W_BAD = 2, W_MORE = 3 };
+enum : int { W_IN = 0, W_LEFT = -1, W_RIGHT = 1, W_BAD = 2, W_MORE = 3, W_FIRST = 4 };
 
 __device__ __forceinline__ int walk_step(const int4 T, int N, int periodic, int &j, float &sig) {
   const int lo = T.y & 0xFFFF, hi = T.y >> 16;
@@ -654,7 +655,10 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
             for (int j = t; j < ne; j += BLOCK) sE32[j] = I.E32[j];
             if (MODE != M_PULLBACK) {
               if (I.uniform) {
-                for (int j = t; j < N; j += BLOCK) sT[j] = make_int4(__float_as_int(I.dtoh32u), 0, 0, 0);
+                // one run spanning the grid: the first step's in-run test then
+                // accepts every move that stays inside a bounded grid
+                for (int j = t; j < N; j += BLOCK)
+                  sT[j] = make_int4(__float_as_int(I.dtoh32u), (N - 1) << 16, 0, 0);
               } else {
                 const bool per = I.bc == 1;
                 for (int j = t; j < N; j += BLOCK) {
@@ -689,19 +693,22 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
       int c[kPPT], kn[kPPT];
       float o[kPPT], vx[kPPT];
       if (full) {
-        const int4 c4 = gload4(P.cell + i0);
-        c[0] = c4.x; c[1] = c4.y; c[2] = c4.z; c[3] = c4.w;
-        if (MODE != M_MCC) {
-          const float4 o4 = gload4(P.off + i0);
-          o[0] = o4.x; o[1] = o4.y; o[2] = o4.z; o[3] = o4.w;
-        }
-        if (MODE != M_DEPOSIT && MODE != M_MCC) {
-          const float4 v4 = gload4(P.vx + i0);
-          vx[0] = v4.x; vx[1] = v4.y; vx[2] = v4.z; vx[3] = v4.w;
-        }
-        if (MODE == M_MCC || MODE == M_FUSED) {
-          const int4 k4 = gload4(P.knext + i0);
-          kn[0] = k4.x; kn[1] = k4.y; kn[2] = k4.z; kn[3] = k4.w;
+#pragma unroll
+        for (int g = 0; g < kPPT; g += 4) {
+          const int4 c4 = gload4(P.cell + i0 + g);
+          c[g] = c4.x; c[g + 1] = c4.y; c[g + 2] = c4.z; c[g + 3] = c4.w;
+          if (MODE != M_MCC) {
+            const float4 o4 = gload4(P.off + i0 + g);
+            o[g] = o4.x; o[g + 1] = o4.y; o[g + 2] = o4.z; o[g + 3] = o4.w;
+          }
+          if (MODE != M_DEPOSIT && MODE != M_MCC) {
+            const float4 v4 = gload4(P.vx + i0 + g);
+            vx[g] = v4.x; vx[g + 1] = v4.y; vx[g + 2] = v4.z; vx[g + 3] = v4.w;
+          }
+          if (MODE == M_MCC || MODE == M_FUSED) {
+            const int4 k4 = gload4(P.knext + i0 + g);
+            kn[g] = k4.x; kn[g + 1] = k4.y; kn[g + 2] = k4.z; kn[g + 3] = k4.w;
+          }
         }
       } else {
 #pragma unroll
@@ -733,17 +740,27 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
                                         : ((1.0f - o[q]) * sE32[j]) + (o[q] * sE32[j + 1]);
           const float v1 = vx[q] + qmdt32 * e;
           const int4 T = sT[j];
-          float sig = o[q] + v1 * __int_as_float(T.x);
-          int jj = j;
-          if (sig < 0.0f || sig >= 1.0f) st[q] = walk_first(G, T, jj, sig);
+          const float sig = o[q] + v1 * __int_as_float(T.x);
+          // First walk step without branches: a move that stays inside the
+          // run around j (j + floor(sigma) within [lo, hi], either direction)
+          // ends at sigma - floor(sigma), moved one cell right when a left move
+          // rounds up to 1 (see walk_step).  Anything else walks below.
+          const float m = floorf(sig);
+          const int jm = j + (int)m;
+          const bool moved = sig < 0.0f || sig >= 1.0f;
+          const bool inrun = fabsf(sig) < kWalkLimit && jm >= (T.y & 0xFFFF) && jm <= (T.y >> 16);
+          const float r = sig - m;
+          const bool up = r >= 1.0f;
           vn[q] = v1;
-          cn[q] = jj;
-          on[q] = sig;
-          more |= st[q] == W_MORE;
+          cn[q] = moved ? (inrun ? (up ? jm + 1 : jm) : j) : j;
+          on[q] = moved ? (inrun ? (up ? 0.0f : r) : sig) : sig;
+          st[q] = (moved && !inrun) ? W_FIRST : W_IN;
+          more |= moved && !inrun;
         }
         if (__ballot(more) != 0) {
 #pragma unroll
           for (int q = 0; q < kPPT; ++q) {
+            if (st[q] == W_FIRST) st[q] = walk_first(G, sT[cn[q]], cn[q], on[q]);
             int guard = 0;
             while (st[q] == W_MORE) {
               if (++guard > 4 * G.N + 64) {
@@ -756,25 +773,20 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
         }
 #pragma unroll
         for (int q = 0; q < kPPT; ++q) {
-          want[q] = false;
-          went[q] = 0;
-          if (c[q] < 0) continue;   // dead slot
-          live_here += 1;
+          const bool live = c[q] >= 0;
           const int ii = (int)(i0 + q);
           const int wall = st[q];
           const float v1 = vn[q];
-          if (wall != W_IN || v1 != v1) {
-            cn[q] = -1;
-            on[q] = o[q];
-            want[q] = true;
-            went[q] = qentry(ii, (wall == W_BAD || v1 != v1) ? 3 : (wall < 0 ? 1 : 2));
-          } else {
+          const bool gone = live && (wall != W_IN || v1 != v1);   // absorbed or non-finite
+          const bool cand = MODE == M_FUSED && live && !gone && coll && kn[q] <= k;
+          live_here += live ? 1u : 0u;
+          want[q] = gone || cand;
+          went[q] = qentry(ii, gone ? ((wall == W_BAD || v1 != v1) ? 3 : (wall < 0 ? 1 : 2)) : 0);
+          cn[q] = gone ? -1 : cn[q];
+          on[q] = gone ? o[q] : on[q];
+          if (live && !gone) {
             const int jj = cn[q];
             const float sig = on[q];
-            if (MODE == M_FUSED && coll && kn[q] <= k) {
-              want[q] = true;
-              went[q] = qentry(ii, 0);
-            }
             if (due_eedf) {
               const double x = I.uniform ? ((double)jj * I.dx + (double)sig * I.dx)
                                          : (I.nodes[jj] + (double)sig * I.h[jj]);
@@ -815,11 +827,14 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
       if constexpr (MODE == M_DEPOSIT || MODE == M_FUSED) dep.flush(sA);
       if constexpr (MODE == M_PUSH || MODE == M_FUSED || MODE == M_PULLBACK) {
         if (full) {
-          if constexpr (MODE != M_PULLBACK) {
-            gstore4(P.cell + i0, cn[0], cn[1], cn[2], cn[3]);
-            gstore4(P.off + i0, on[0], on[1], on[2], on[3]);
+#pragma unroll
+          for (int g = 0; g < kPPT; g += 4) {
+            if constexpr (MODE != M_PULLBACK) {
+              gstore4(P.cell + i0 + g, cn[g], cn[g + 1], cn[g + 2], cn[g + 3]);
+              gstore4(P.off + i0 + g, on[g], on[g + 1], on[g + 2], on[g + 3]);
+            }
+            gstore4(P.vx + i0 + g, vn[g], vn[g + 1], vn[g + 2], vn[g + 3]);
           }
-          gstore4(P.vx + i0, vn[0], vn[1], vn[2], vn[3]);
         } else {
 #pragma unroll
           for (int q = 0; q < kPPT; ++q) {
@@ -839,17 +854,20 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
       double x[kPPT], vx[kPPT];
       int kn[kPPT];
       if (full) {
-        const double2 xa = gload2(P.x + i0);
-        const double2 xb = gload2(P.x + i0 + 2);
-        x[0] = xa.x; x[1] = xa.y; x[2] = xb.x; x[3] = xb.y;
-        if (MODE != M_DEPOSIT && MODE != M_MCC) {
-          const double2 va = gload2(P.vx + i0);
-          const double2 vb = gload2(P.vx + i0 + 2);
-          vx[0] = va.x; vx[1] = va.y; vx[2] = vb.x; vx[3] = vb.y;
-        }
-        if (MODE == M_MCC || MODE == M_FUSED) {
-          const int4 k4 = gload4(P.knext + i0);
-          kn[0] = k4.x; kn[1] = k4.y; kn[2] = k4.z; kn[3] = k4.w;
+#pragma unroll
+        for (int g = 0; g < kPPT; g += 4) {
+          const double2 xa = gload2(P.x + i0 + g);
+          const double2 xb = gload2(P.x + i0 + g + 2);
+          x[g] = xa.x; x[g + 1] = xa.y; x[g + 2] = xb.x; x[g + 3] = xb.y;
+          if (MODE != M_DEPOSIT && MODE != M_MCC) {
+            const double2 va = gload2(P.vx + i0 + g);
+            const double2 vb = gload2(P.vx + i0 + g + 2);
+            vx[g] = va.x; vx[g + 1] = va.y; vx[g + 2] = vb.x; vx[g + 3] = vb.y;
+          }
+          if (MODE == M_MCC || MODE == M_FUSED) {
+            const int4 k4 = gload4(P.knext + i0 + g);
+            kn[g] = k4.x; kn[g + 1] = k4.y; kn[g + 2] = k4.z; kn[g + 3] = k4.w;
+          }
         }
       } else {
 #pragma unroll
@@ -927,12 +945,11 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
       if constexpr (MODE == M_DEPOSIT || MODE == M_FUSED) dep.flush(sA);
       if constexpr (MODE == M_PUSH || MODE == M_FUSED || MODE == M_PULLBACK) {
         if (full) {
-          if constexpr (MODE != M_PULLBACK) {
-            gstore2(P.x + i0, xn[0], xn[1]);
-            gstore2(P.x + i0 + 2, xn[2], xn[3]);
+#pragma unroll
+          for (int g = 0; g < kPPT; g += 2) {
+            if constexpr (MODE != M_PULLBACK) gstore2(P.x + i0 + g, xn[g], xn[g + 1]);
+            gstore2(P.vx + i0 + g, vn[g], vn[g + 1]);
           }
-          gstore2(P.vx + i0, vn[0], vn[1]);
-          gstore2(P.vx + i0 + 2, vn[2], vn[3]);
         } else {
 #pragma unroll
           for (int q = 0; q < kPPT; ++q) {
@@ -946,10 +963,12 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
       }
     }
     if constexpr (MODE == M_PUSH || MODE == M_MCC || MODE == M_FUSED) {
+      if (__ballot(want[0] || want[1] || want[2] || want[3]) != 0) {
 #pragma unroll
-      for (int q = 0; q < kPPT; ++q) {
-        enqueue(want[q], went[q]);   // at most 64 more: kSpill - 1 + 64 <= kWaveQ
-        spill(false);
+        for (int q = 0; q < kPPT; ++q) {
+          enqueue(want[q], went[q]);   // at most 64 more: kSpill - 1 + 64 <= kWaveQ
+          spill(false);
+        }
       }
     }
   }
