@@ -143,6 +143,36 @@ def run_serving(n_req, scale, cycles, rate, slots):
     return out
 
 
+def run_small_workloads():
+    """Workloads 1 and 2 (cache-resident sizes; the HBM roofline does not apply):
+    wall-clock particle-steps/s of their full runs, graph-replayed."""
+    import torch
+    from paper_2308_13092_amd import Context, configs
+    out = {}
+
+    def timed(cfg, steps):
+        ctx = Context([cfg])
+        ctx.step(20)
+        torch.cuda.synchronize()
+        d0 = ctx.diagnostics(0)["particle_steps"]
+        t0 = time.perf_counter()
+        ctx.step(steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ps = ctx.diagnostics(0)["particle_steps"] - d0
+        ctx.close()
+        return dict(value=ps / el, ms_per_step=1e3 * el / steps, steps=steps)
+
+    for g, name in ((0, "ec"), (1, "mc")):
+        out[f"small_fp64_{name}"] = timed(configs.small(gather=g, precision=0), configs.SMALL_STEPS)
+    for prec, name in ((0, "fp64"), (1, "fp32")):
+        out[f"resolved_512_{name}"] = timed(configs.resolved(precision=prec), configs.RESOLVED_STEPS)
+    out["resolved_64_ec_fp32"] = timed(configs.resolved(precision=1, n_cells=64), configs.RESOLVED_STEPS)
+    out["note"] = ("small: 128 cells, 12800 + 12800 particles, dt = T_RF/400, 2000 steps; resolved: 512 "
+                   "(or 64) cells, 262144 + 262144 particles, dt = T_RF/800, 16000 steps")
+    return out
+
+
 def cpu_baseline(n_per_species=2_000_000, seconds=12.0, min_steps=3):
     """The oracle as it stands, on one host core, stepped until ``seconds``
     of CPU work have elapsed (at least ``min_steps`` steps)."""
@@ -178,6 +208,7 @@ def main():
     ap.add_argument("--sweep-steps", type=int, default=2000)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--no-small", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the discharge "
@@ -200,7 +231,7 @@ def main():
     traffic = None if tr is None else tr["bytes_per_launch"]
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
-                    kernel="k_particles<F32, M_FUSED>", avg_launch_ms=round(avg_ms, 4),
+                    kernel=f"k_particles<F32, M_FUSED, {r32['tuning']['block']}>", avg_launch_ms=round(avg_ms, 4),
                     particles_per_launch=round(per_launch, 1), bytes_per_particle_step=B_ALG[1],
                     field_ms_per_launch=round(kt["field_ms"] / max(kt["field_launches"], 1), 4),
                     drain_ms_per_launch=round(kt["drain_ms"] / max(kt["drain_launches"], 1), 4),
@@ -223,6 +254,12 @@ def main():
         serving = run_serving(a.serve_requests, 0.1, (5, 20), 20.0, 256)
         print(f"[bench] serving: p50 {serving['p50_s']:.3f} s, p99 {serving['p99_s']:.3f} s, "
               f"{serving['throughput']:.4g} p-s/s", file=sys.stderr, flush=True)
+
+    small = None
+    if not a.no_small:
+        small = run_small_workloads()
+        print("[bench] small/resolved: " + ", ".join(f"{k} {v['value']:.3g}" for k, v in small.items()
+                                                    if isinstance(v, dict)), file=sys.stderr, flush=True)
 
     cpu = None if a.no_cpu else cpu_baseline()
     line = {
@@ -248,6 +285,7 @@ def main():
         "fp64_plain": fp64,
         "batched_sweep": sweep,
         "serving": serving,
+        "small_workloads": small,
         "status": r32["status"],
     }
     print(json.dumps(line))
