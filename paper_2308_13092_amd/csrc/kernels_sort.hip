@@ -18,7 +18,8 @@
 namespace ecpic {
 
 constexpr int kSB = 256;      // threads per workgroup
-constexpr int kSPPT = 4;      // particles per thread per tile
+constexpr int kSPPT = 4;      // particles per thread per tile (a multiple of 4)
+static_assert(kSPPT % 4 == 0, "records are loaded 4 at a time");
 constexpr int kSTile = kSB * kSPPT;
 
 struct SortSmem {
@@ -358,7 +359,8 @@ k_sort_scatter(const InstDev *__restrict__ insts, InstState *__restrict__ states
     const int64_t i0 = (tile - sm.seg_prefix[seg]) * kSTile + (int64_t)threadIdx.x * kSPPT;
     typename RecOf<P>::T r[kSPPT];
     bool ok[kSPPT];
-    load_recs(src, i0, ext, r, ok);
+#pragma unroll
+    for (int g = 0; g < kSPPT; g += 4) load_recs(src, i0 + g, ext, r + g, ok + g);
     int key[kSPPT];
     unsigned int rank[kSPPT];
     // Rank of each particle among the tile's particles of its cell: one LDS
