@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define PIC_ABI_VERSION 1
+#define PIC_ABI_VERSION 2
 
 typedef struct pic_ctx pic_ctx;  /* opaque; owns host-side metadata only */
 
@@ -101,6 +101,14 @@ typedef struct pic_config {
   double eedf_width_m;    /* width of the central sampling window; 0 -> 1 mm           */
   int64_t k_stop;         /* the instance stops advancing at this step; 0 = never      */
   double growth_limit;    /* PIC_EGROWTH when live > growth_limit x initial; 0 -> 10   */
+  /* Impact distributions of absorbed particles (Section 3a: ion energy and
+     angle at the electrodes), recorded per species and wall on the steps that
+     are averaged (avg_every > 0, k >= avg_start). */
+  int32_t impact_bins;       /* energy bins over [0, impact_emax_ev) plus one overflow
+                                bin (<= PIC_MAX_EEDF_BINS); 0 -> 200                   */
+  int32_t impact_angle_bins; /* bins of the angle to the wall normal over [0, 90] deg
+                                (<= PIC_MAX_EEDF_BINS); 0 -> 90                        */
+  double impact_emax_ev;     /* 0 -> 1000 eV                                           */
 } pic_config;
 
 #define PIC_MAX_CELLS 2048
@@ -241,6 +249,16 @@ pic_status pic_get_fields(pic_ctx *ctx, int32_t inst, int64_t *A_e, int64_t *A_i
  * may be NULL.  Synchronises. */
 pic_status pic_profiles(pic_ctx *ctx, int32_t inst, double *ne, double *ni, double *phi,
                         int64_t *eedf);
+
+/* Impact distributions of one species at one wall (0 = x = 0, the powered
+ * electrode; 1 = x = L) over the averaged steps (Section 3a): energy counts
+ * int64[impact_bins + 1] (the last bin counts E >= impact_emax_ev) and angle
+ * counts int64[impact_angle_bins] of theta = acos(|vx| / |v|).  Energy bin
+ * floor(E * impact_bins / impact_emax_ev) with E = (m / 2e) |v|^2 in eV;
+ * angle bin floor(theta_deg * impact_angle_bins / 90), theta = 90 in the last.
+ * Either pointer may be NULL.  Synchronises. */
+pic_status pic_impacts(pic_ctx *ctx, int32_t inst, int32_t species, int32_t wall, int64_t *energy,
+                       int64_t *angle);
 
 /* Re-initialise slot inst with cfg (n_cells == 0 empties it), taking memory
  * from the arena pool.  PIC_ENOMEM when the pool cannot hold it. */

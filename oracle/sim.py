@@ -31,8 +31,23 @@ DEFAULTS = dict(
     n_per_species=12800, weight_m2=0.0, dt_s=1.0 / (400 * 13.56e6), gather=0, precision=0,
     gamma_see=0.0, t_see_ev=2.0, seed=1, n_species=2, collisions=1, pullback=0,
     nu_max_e=0.0, nu_max_i=0.0, avg_start=0, avg_every=0, eedf_every=0, eedf_bins=200,
-    eedf_emax_ev=50.0, eedf_width_m=1e-3,
+    eedf_emax_ev=50.0, eedf_width_m=1e-3, impact_bins=0, impact_angle_bins=0, impact_emax_ev=0.0,
 )
+
+
+def impact_bins(en, vx, v2, nb, na, emax):
+    """Histogram bins of absorbed particles (the ion-impact energy and angle
+    data of Section 3a): energy E in eV binned as floor(E * nb / emax) with one
+    overflow bin nb; angle to the wall normal theta = acos(|vx| / |v|) in
+    degrees, binned as floor(theta * na / 90), theta = 90 in the last bin."""
+    fe = np.floor(en * (nb / emax))
+    be = np.where(fe < nb, fe, nb).astype(np.int64)
+    cth = np.ones_like(v2)
+    pos = v2 > 0.0
+    cth[pos] = np.minimum(1.0, np.abs(vx[pos]) / np.sqrt(v2[pos]))
+    th = np.arccos(cth) * (180.0 / math.pi)
+    ba = np.minimum(np.floor(th * (na / 90.0)).astype(np.int64), na - 1)
+    return be, ba
 
 
 def resolve(cfg):
@@ -82,6 +97,12 @@ class Sim:
         self.eedf_samples = 0
         self.absorbed = np.zeros((2, 2), dtype=np.int64)      # [species][wall: 0 left, 1 right]
         self.absorbed_energy_ev = np.zeros((2, 2))
+        # impact distributions [species][wall]: energy (bins + overflow), angle
+        self.imp_nb = int(c["impact_bins"] or 200)
+        self.imp_na = int(c["impact_angle_bins"] or 90)
+        self.imp_emax = float(c["impact_emax_ev"] or 1000.0)
+        self.impact_e = np.zeros((2, 2, self.imp_nb + 1), dtype=np.int64)
+        self.impact_a = np.zeros((2, 2, self.imp_na), dtype=np.int64)
         self.see_emitted = 0
         self.created = 0
         self.mcc = [MccCounts(), MccCounts()]
@@ -191,7 +212,12 @@ class Sim:
                     vya = moved.vy[mw].astype(np.float64)
                     vza = moved.vz[mw].astype(np.float64)
                     v2 = (vxa * vxa + vya * vya) + vza * vza
-                    self.absorbed_energy_ev[s, wi] += float(np.sum((0.5 * self.m[s] / ph.QE) * v2))
+                    en = (0.5 * self.m[s] / ph.QE) * v2
+                    self.absorbed_energy_ev[s, wi] += float(np.sum(en))
+                    if c["avg_every"] > 0 and k >= c["avg_start"] and len(en):
+                        be, ba = impact_bins(en, vxa, v2, self.imp_nb, self.imp_na, self.imp_emax)
+                        np.add.at(self.impact_e[s, wi], be, 1)
+                        np.add.at(self.impact_a[s, wi], ba, 1)
                 if s == 1 and self.nsp > 1:
                     see_new = emit_secondaries(g, moved.id[gone], wall[gone], k, self.seed,
                                                c["gamma_see"], c["t_see_ev"], self.dt, self.prec,

@@ -33,6 +33,7 @@ class pic_config(C.Structure):
         ("nu_max_i", C.c_double), ("avg_start", C.c_int64), ("avg_every", C.c_int32),
         ("eedf_every", C.c_int32), ("eedf_bins", C.c_int32), ("eedf_emax_ev", C.c_double),
         ("eedf_width_m", C.c_double), ("k_stop", C.c_int64), ("growth_limit", C.c_double),
+        ("impact_bins", C.c_int32), ("impact_angle_bins", C.c_int32), ("impact_emax_ev", C.c_double),
     ]
 
 
@@ -92,6 +93,7 @@ SIGNATURES = [
     ("pic_get_fields", C.c_int, [_CTX, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.c_void_p]),
     ("pic_profiles", C.c_int, [_CTX, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("pic_impacts", C.c_int, [_CTX, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
     ("pic_slot_reset", C.c_int, [_CTX, C.c_int32, C.POINTER(pic_config)]),
     ("pic_slot_release", C.c_int, [_CTX, C.c_int32]),
     ("pic_slot_bytes", C.c_size_t, [C.POINTER(pic_config)]),
@@ -339,6 +341,17 @@ class Context:
         st = self.lib.pic_profiles(self.ctx, inst, _ptr(out["ne"]), _ptr(out["ni"]),
                                    _ptr(out["phi"]), _ptr(out["eedf"]))
         self._check(st, "pic_profiles", allow=(PIC_ECAPACITY, PIC_ENONFINITE, PIC_EGROWTH))
+        return out
+
+    def impacts(self, inst, species, wall):
+        """Energy (bins + overflow) and angle counts of particles of ``species``
+        absorbed at ``wall`` (0: x = 0, 1: x = L) over the averaged steps."""
+        cfg = self.cfgs[inst]
+        nb = int(cfg.get("impact_bins", 0) or 200)
+        na = int(cfg.get("impact_angle_bins", 0) or 90)
+        out = dict(energy=np.zeros(nb + 1, np.int64), angle=np.zeros(na, np.int64))
+        st = self.lib.pic_impacts(self.ctx, inst, species, wall, _ptr(out["energy"]), _ptr(out["angle"]))
+        self._check(st, "pic_impacts", allow=(PIC_ECAPACITY, PIC_ENONFINITE, PIC_EGROWTH))
         return out
 
     # -- slots, tuning, timing ------------------------------------------------

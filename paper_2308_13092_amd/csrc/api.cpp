@@ -84,11 +84,15 @@ struct SlotHost {
 
 // Grid block layout (offsets relative to the slot block).
 struct GridLayout {
-  size_t nodes, h, V, dtoh, rf, rb, runs, A[2][2], phi, E64, E32, accA[2], acc_phi, eedf, scount[2],
+  size_t nodes, h, V, dtoh, rf, rb, runs, A[2][2], phi, E64, E32, accA[2], acc_phi, eedf, impact, scount[2],
       scursor[2], queue[2], particles, total;
 };
 
 int eff_bins(const pic_config &c) { return c.eedf_bins > 0 ? c.eedf_bins : 200; }
+int eff_ibins(const pic_config &c) { return c.impact_bins > 0 ? c.impact_bins : 200; }
+int eff_abins(const pic_config &c) { return c.impact_angle_bins > 0 ? c.impact_angle_bins : 90; }
+// Impact counters per (species, wall): energy bins + overflow, then angle bins.
+size_t impact_row(const pic_config &c) { return (size_t)eff_ibins(c) + 1 + (size_t)eff_abins(c); }
 int64_t eff_cap(const pic_config &c) {
   int64_t cap = c.capacity > 0 ? c.capacity : 2 * c.n_per_species + 4096;
   return (cap + 63) / 64 * 64;
@@ -116,6 +120,7 @@ GridLayout layout(const pic_config &c) {
   g.accA[1] = take(8 * n1);
   g.acc_phi = take(8 * n1);
   g.eedf = take(8 * (size_t)eff_bins(c));
+  g.impact = take(8 * 4 * impact_row(c));
   for (int s = 0; s < 2; ++s) g.scount[s] = take(8 * n1);
   for (int s = 0; s < 2; ++s) g.scursor[s] = take(8 * n1);
   for (int s = 0; s < 2; ++s) g.queue[s] = take((s == 0 || c.n_species != 1) ? 4 * (size_t)eff_cap(c) : 0);
@@ -160,6 +165,10 @@ std::string validate(const pic_config &c) {
   if (c.collisions && (!(c.p_pa >= 0.0) || !(c.t_gas_k > 0.0))) return "need p_pa >= 0 and t_gas_k > 0";
   if (!(c.gamma_see >= 0.0 && c.gamma_see <= 1.0)) return "gamma_see must be in [0, 1]";
   if (c.eedf_bins < 0 || c.eedf_bins > PIC_MAX_EEDF_BINS) return "eedf_bins out of range";
+  if (c.impact_bins < 0 || c.impact_bins > PIC_MAX_EEDF_BINS || c.impact_angle_bins < 0 ||
+      c.impact_angle_bins > PIC_MAX_EEDF_BINS)
+    return "impact bins out of range";
+  if (!(c.impact_emax_ev >= 0.0) || !std::isfinite(c.impact_emax_ev)) return "impact_emax_ev must be >= 0";
   if (c.sort_interval < 0 || c.avg_every < 0 || c.eedf_every < 0) return "negative interval";
   if (c.nu_max_e < 0.0 || c.nu_max_i < 0.0) return "nu_max must be >= 0";
   if (!std::isfinite(c.v_rf) || !std::isfinite(c.f_rf) || !std::isfinite(c.phase))
@@ -404,6 +413,11 @@ static pic_status setup_slot(pic_ctx *c, int i, const pic_config &cfg) {
   I.accA[1] = (double *)(base + g.accA[1]);
   I.acc_phi = (double *)(base + g.acc_phi);
   I.eedf = (unsigned long long *)(base + g.eedf);
+  I.impact = (unsigned long long *)(base + g.impact);
+  I.imp_bins = eff_ibins(cfg);
+  I.imp_abins = eff_abins(cfg);
+  I.imp_escale = (double)I.imp_bins / (cfg.impact_emax_ev > 0.0 ? cfg.impact_emax_ev : 1000.0);
+  I.imp_ascale = (double)I.imp_abins / 90.0;
   for (int s = 0; s < 2; ++s) {
     I.scount[s] = (unsigned long long *)(base + g.scount[s]);
     I.scursor[s] = (unsigned long long *)(base + g.scursor[s]);
@@ -1022,6 +1036,24 @@ pic_status pic_profiles(pic_ctx *c, int32_t inst, double *ne, double *ni, double
   }
   if (eedf) HIP_TRY(c, hipMemcpy(eedf, I.eedf, 8 * (size_t)I.eedf_bins, hipMemcpyDeviceToHost));
   (void)sl;
+  return status_of(S.status);
+}
+
+pic_status pic_impacts(pic_ctx *c, int32_t inst, int32_t species, int32_t wall, int64_t *energy,
+                       int64_t *angle) {
+  pic_status r = check_inst(c, inst);
+  if (r != PIC_OK) return r;
+  const InstDev &I = c->host_inst[inst];
+  if (species < 0 || species > 1 || wall < 0 || wall > 1)
+    return fail(c, PIC_EINVAL, "species and wall must be 0 or 1");
+  InstState S;
+  r = read_state(c, inst, S);
+  if (r != PIC_OK) return r;
+  const size_t row = (size_t)I.imp_bins + 1 + (size_t)I.imp_abins;
+  const unsigned long long *src = I.impact + (size_t)(2 * species + wall) * row;
+  if (energy) HIP_TRY(c, hipMemcpy(energy, src, 8 * ((size_t)I.imp_bins + 1), hipMemcpyDeviceToHost));
+  if (angle)
+    HIP_TRY(c, hipMemcpy(angle, src + I.imp_bins + 1, 8 * (size_t)I.imp_abins, hipMemcpyDeviceToHost));
   return status_of(S.status);
 }
 

@@ -83,6 +83,9 @@ struct InstDev {
   float *E32;
   double *accA[2], *acc_phi;
   unsigned long long *eedf;
+  unsigned long long *impact;  // [species][wall][energy bins + 1 | angle bins]
+  int32_t imp_bins, imp_abins;
+  double imp_escale, imp_ascale;  // bins / emax (1/eV), angle bins / 90 (1/deg)
   unsigned long long *scount[2], *scursor[2];
   int *queue[2];               // per-species queue of particles for the drain kernel
   // particles

@@ -975,6 +975,21 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
   if (seg >= 0) flush();
 }
 
+// Energy and angle histograms of an absorbed particle (species sp, wall wi):
+// energy bin floor(E * bins / emax), the last bin for E >= emax; angle to the
+// wall normal theta = acos(|vx| / |v|), bin floor(theta_deg * abins / 90).
+__device__ __forceinline__ void record_impact(CInst &I, int sp, int wi, double en, double vx, double v2) {
+  const int nb = I.imp_bins, na = I.imp_abins;
+  unsigned long long *row = I.impact + (size_t)(2 * sp + wi) * (size_t)(nb + 1 + na);
+  const double fe = floor(en * I.imp_escale);
+  const int be = (fe < (double)nb) ? (int)fe : nb;
+  const double c = (v2 > 0.0) ? fmin(1.0, fabs(vx) / sqrt(v2)) : 1.0;
+  const double th = acos(c) * (180.0 / 3.14159265358979323846);
+  const int ba = min((int)floor(th * I.imp_ascale), na - 1);
+  atomicAdd(&row[be], 1ull);
+  atomicAdd(&row[nb + 1 + ba], 1ull);
+}
+
 // Velocity and id of particle i.
 __device__ __forceinline__ void load_particle(const P32 &P, int64_t i, double &vx, double &vy,
                                               double &vz, uint64_t &id) {
@@ -1011,8 +1026,10 @@ __device__ void drain_one(CInst &I, InstState &S, Smem &sm, int sp, int buf, int
   if (kind != 0) {
     const int wi = kind - 1;
     atomicAdd(&sm.ctr[C_ABS + 2 * sp + wi], 1ull);
-    const double en = (0.5 * I.mass[sp] / kQE) * ((vxd * vxd + vy * vy) + vz * vz);
+    const double v2 = (vxd * vxd + vy * vy) + vz * vz;
+    const double en = (0.5 * I.mass[sp] / kQE) * v2;
     atomicAdd(&sm.ctr[C_EABS + 2 * sp + wi], (unsigned long long)rint(en * 65536.0));
+    if (I.avg_every > 0 && k >= I.avg_start) record_impact(I, sp, wi, en, vxd, v2);
     if (sp == 1 && I.gamma_see > 0.0 && I.nsp > 1)
       emit_secondary<F>(I, S, sm, id, wi == 0 ? -1 : 1, k, buf, MODE == M_FUSED,
                         I.A[(k + 1) & 1][0]);

@@ -249,3 +249,30 @@ def test_diagnostics_against_oracle(gpu):
         assert d["kinetic_j_m2"][s] == pytest.approx(ref.kinetic_energy(s), rel=1e-6)
     assert d["field_j_m2"] == pytest.approx(ref.field_energy, rel=1e-9)
     assert d["particle_steps"] > 0
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_impact_distributions_against_oracle(gpu, prec):
+    """Energy and angle histograms of absorbed particles over 30 steps from the
+    same initial load: totals equal the absorbed counts on both sides, and the
+    histograms agree up to particles whose bin depends on the last ulp of acos
+    (or whose trajectories the field's rounding has moved apart)."""
+    note("impacts", prec)
+    cfg = case_cfg(prec, "uniform", n=20_000, avg_every=1, impact_bins=100, impact_angle_bins=45,
+                   impact_emax_ev=200.0)
+    ctx = Context()([cfg])
+    ref = Sim(cfg)
+    ctx.step(30)
+    ref.run(30)
+    d = ctx.diagnostics()
+    for s in range(2):
+        for w in range(2):
+            h = ctx.impacts(0, s, w)
+            assert h["energy"].sum() == d["absorbed"][s][w]
+            assert h["angle"].sum() == d["absorbed"][s][w]
+            tot = max(int(ref.absorbed[s, w]), 1)
+            assert abs(int(d["absorbed"][s][w]) - int(ref.absorbed[s, w])) <= 2 + tot // 100
+            de = np.abs(h["energy"] - ref.impact_e[s, w]).sum()
+            da = np.abs(h["angle"] - ref.impact_a[s, w]).sum()
+            note("impact", s, w, int(ref.absorbed[s, w]), int(de), int(da))
+            assert de <= 4 + tot // 50 and da <= 4 + tot // 50
