@@ -250,6 +250,16 @@ pic_status pic_get_fields(pic_ctx *ctx, int32_t inst, int64_t *A_e, int64_t *A_i
 pic_status pic_profiles(pic_ctx *ctx, int32_t inst, double *ne, double *ni, double *phi,
                         int64_t *eedf);
 
+/* Velocity moments and power of one species over the averaged steps
+ * (Section 3a), sampled from x^k, v^{k-1/2} and E^k: at the N+1 nodes the mean
+ * x-velocity ux = sum w vx / sum w (m/s) and the x-temperature
+ * tx = (m/e)(sum w vx^2 / sum w - ux^2) (eV), w the particles' linear
+ * weights; per cell the power density given to the species,
+ * q W sum_{p in cell j} vx_p E(x_p) / h_j averaged over the samples (W/m^3,
+ * E(x) the gathered field).  Any pointer may be NULL.  Synchronises. */
+pic_status pic_moments(pic_ctx *ctx, int32_t inst, int32_t species, double *ux, double *tx,
+                       double *power);
+
 /* Impact distributions of one species at one wall (0 = x = 0, the powered
  * electrode; 1 = x = L) over the averaged steps (Section 3a): energy counts
  * int64[impact_bins + 1] (the last bin counts E >= impact_emax_ev) and angle

@@ -20,10 +20,10 @@ import math
 import numpy as np
 
 from . import physics as ph
-from .pic import (FP64, GATHER_EC, TAG_CHILD, TWO_M32, Grid, MccCounts, Species,
+from .pic import (BC_PERIODIC, FP64, GATHER_EC, TAG_CHILD, TWO_M32, Grid, MccCounts, Species,
                   collide_electrons, collide_ions, deposit_species, draw, emit_secondaries,
                   field_ec, field_mc, gas_velocity, gather_fp32, gather_fp64, ids_from_words,
-                  init_species, next_candidate, node_charge, poisson, push_fp32, push_fp64)
+                  init_species, locate, next_candidate, node_charge, poisson, push_fp32, push_fp64)
 
 DEFAULTS = dict(
     n_cells=128, bc=0, nodes=None, gap_m=0.025, v_rf=200.0, f_rf=13.56e6, phase=0.0,
@@ -92,6 +92,10 @@ class Sim:
         N = g.N
         self.acc_A = [np.zeros(N + 1) for _ in range(2)]
         self.acc_phi = np.zeros(N + 1)
+        # velocity moments (nodes) and power (cells) of the averaged steps
+        self.acc_m1 = [np.zeros(N + 1) for _ in range(2)]
+        self.acc_m2 = [np.zeros(N + 1) for _ in range(2)]
+        self.acc_p = [np.zeros(N) for _ in range(2)]
         self.n_samples = 0
         self.eedf = np.zeros(int(c["eedf_bins"]), dtype=np.int64)
         self.eedf_samples = 0
@@ -159,8 +163,52 @@ class Sim:
         if c["avg_every"] > 0 and k >= c["avg_start"] and (k - c["avg_start"]) % c["avg_every"] == 0:
             for s in range(self.nsp):
                 self.acc_A[s] += self.A[s].astype(np.float64)
+                self._accumulate_moments(s)
             self.acc_phi += self.phi
             self.n_samples += 1
+
+    def _accumulate_moments(self, s):
+        """Section 3a moments from x^k, v^{k-1/2} and E^k: sum w vx and
+        sum w vx^2 at the nodes with the linear weights w = 1 - xi, xi, and per
+        cell sum vx E(x) with the gathered field (E_j for EC, linear for MC)."""
+        sp = self.sp[s]
+        if sp.n == 0:
+            return
+        if self.prec == FP64:
+            j, xi = locate(self.grid, sp.x)
+        else:
+            j = sp.cell.astype(np.int64)
+            xi = sp.off.astype(np.float64)
+        vx = sp.vx.astype(np.float64)
+        w0, w1 = 1.0 - xi, xi
+        np.add.at(self.acc_m1[s], j, w0 * vx)
+        np.add.at(self.acc_m1[s], j + 1, w1 * vx)
+        np.add.at(self.acc_m2[s], j, w0 * (vx * vx))
+        np.add.at(self.acc_m2[s], j + 1, w1 * (vx * vx))
+        E = self.E
+        e = E[j] if self.gather == GATHER_EC else (1.0 - xi) * E[j] + xi * E[j + 1]
+        np.add.at(self.acc_p[s], j, vx * e)
+
+    def moments(self, s):
+        """Mean x-velocity (m/s) and x-temperature (eV) at the nodes, power
+        density (W/m^3) per cell: ratios of the averaged sums."""
+        g = self.grid
+        N = g.N
+        m1 = self.acc_m1[s].copy()
+        m2 = self.acc_m2[s].copy()
+        if g.bc == BC_PERIODIC:          # node N is node 0
+            m1[0] += m1[N]
+            m1[N] = m1[0]
+            m2[0] += m2[N]
+            m2[N] = m2[0]
+        w = self.acc_A[s] * TWO_M32
+        ok = w > 0
+        ux = np.zeros(N + 1)
+        tx = np.zeros(N + 1)
+        ux[ok] = m1[ok] / w[ok]
+        tx[ok] = (self.m[s] / ph.QE) * (m2[ok] / w[ok] - ux[ok] * ux[ok])
+        power = (self.qW[s] * self.acc_p[s]) / (g.h * max(self.n_samples, 1))
+        return dict(ux=ux, tx=tx, power=power)
 
     def _eedf_due(self):
         c = self.cfg

@@ -94,6 +94,7 @@ SIGNATURES = [
                                  C.c_void_p]),
     ("pic_profiles", C.c_int, [_CTX, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("pic_impacts", C.c_int, [_CTX, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
+    ("pic_moments", C.c_int, [_CTX, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("pic_slot_reset", C.c_int, [_CTX, C.c_int32, C.POINTER(pic_config)]),
     ("pic_slot_release", C.c_int, [_CTX, C.c_int32]),
     ("pic_slot_bytes", C.c_size_t, [C.POINTER(pic_config)]),
@@ -341,6 +342,17 @@ class Context:
         st = self.lib.pic_profiles(self.ctx, inst, _ptr(out["ne"]), _ptr(out["ni"]),
                                    _ptr(out["phi"]), _ptr(out["eedf"]))
         self._check(st, "pic_profiles", allow=(PIC_ECAPACITY, PIC_ENONFINITE, PIC_EGROWTH))
+        return out
+
+    def moments(self, inst, species):
+        """Averaged mean x-velocity and x-temperature at the nodes and power
+        density per cell of one species."""
+        cfg = self.cfgs[inst]
+        N = int(cfg["n_cells"]) if cfg.get("nodes") is None else len(cfg["nodes"]) - 1
+        out = dict(ux=np.zeros(N + 1), tx=np.zeros(N + 1), power=np.zeros(N))
+        st = self.lib.pic_moments(self.ctx, inst, species, _ptr(out["ux"]), _ptr(out["tx"]),
+                                  _ptr(out["power"]))
+        self._check(st, "pic_moments", allow=(PIC_ECAPACITY, PIC_ENONFINITE, PIC_EGROWTH))
         return out
 
     def impacts(self, inst, species, wall):

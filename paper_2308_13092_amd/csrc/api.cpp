@@ -84,7 +84,8 @@ struct SlotHost {
 
 // Grid block layout (offsets relative to the slot block).
 struct GridLayout {
-  size_t nodes, h, V, dtoh, rf, rb, runs, A[2][2], phi, E64, E32, accA[2], acc_phi, eedf, impact, scount[2],
+  size_t nodes, h, V, dtoh, rf, rb, runs, A[2][2], phi, E64, E32, accA[2], acc_phi, accM1[2], accM2[2],
+      accP[2], eedf, impact, scount[2],
       scursor[2], queue[2], particles, total;
 };
 
@@ -119,6 +120,11 @@ GridLayout layout(const pic_config &c) {
   g.accA[0] = take(8 * n1);
   g.accA[1] = take(8 * n1);
   g.acc_phi = take(8 * n1);
+  for (int s = 0; s < 2; ++s) {
+    g.accM1[s] = take(8 * n1);
+    g.accM2[s] = take(8 * n1);
+    g.accP[s] = take(8 * N);
+  }
   g.eedf = take(8 * (size_t)eff_bins(c));
   g.impact = take(8 * 4 * impact_row(c));
   for (int s = 0; s < 2; ++s) g.scount[s] = take(8 * n1);
@@ -412,6 +418,11 @@ static pic_status setup_slot(pic_ctx *c, int i, const pic_config &cfg) {
   I.accA[0] = (double *)(base + g.accA[0]);
   I.accA[1] = (double *)(base + g.accA[1]);
   I.acc_phi = (double *)(base + g.acc_phi);
+  for (int s = 0; s < 2; ++s) {
+    I.accM1[s] = (double *)(base + g.accM1[s]);
+    I.accM2[s] = (double *)(base + g.accM2[s]);
+    I.accP[s] = (double *)(base + g.accP[s]);
+  }
   I.eedf = (unsigned long long *)(base + g.eedf);
   I.impact = (unsigned long long *)(base + g.impact);
   I.imp_bins = eff_ibins(cfg);
@@ -539,10 +550,21 @@ static pic_status ev_end(pic_ctx *c) {
 }
 
 // One step (and the sort when `sort`) as plain launches on stream st.
+// Whether any slot accumulates averaged profiles (the moments kernel runs).
+static bool any_averaging(const pic_ctx *c) {
+  for (int i = 0; i < c->n_inst; ++i)
+    if (c->slots[i].used && c->host_inst[i].avg_every > 0) return true;
+  return false;
+}
+
 static pic_status enqueue_step(pic_ctx *c, hipStream_t st, bool sort, bool timed) {
   if (timed) { pic_status r = ev_begin(c, 0); if (r) return r; }
   launch_field(c->d_inst, c->d_state, c->n_inst, 3, st);
   HIP_TRY(c, hipGetLastError());
+  if (any_averaging(c)) {
+    launch_moments(c->d_inst, c->d_state, c->n_inst, c->prec, sort_grid(c), c->max_n, st);
+    HIP_TRY(c, hipGetLastError());
+  }
   if (timed) { pic_status r = ev_end(c); if (r) return r; r = ev_begin(c, 1); if (r) return r; }
   HIP_TRY(c, launch_particles(c->d_inst, c->d_state, c->n_inst, c->prec, M_FUSED, c->tune.block,
                               particle_grid(c), c->max_n, c->d_done, st));
@@ -724,6 +746,10 @@ pic_status pic_poisson(pic_ctx *c) {
   if (!c->deposit_current) return fail(c, PIC_ESTATE, "deposit is stale: call pic_deposit first");
   launch_field(c->d_inst, c->d_state, c->n_inst, 1, c->stream);
   HIP_TRY(c, hipGetLastError());
+  if (any_averaging(c)) {
+    launch_moments(c->d_inst, c->d_state, c->n_inst, c->prec, sort_grid(c), c->max_n, c->stream);
+    HIP_TRY(c, hipGetLastError());
+  }
   return PIC_OK;
 }
 
@@ -1036,6 +1062,40 @@ pic_status pic_profiles(pic_ctx *c, int32_t inst, double *ne, double *ni, double
   }
   if (eedf) HIP_TRY(c, hipMemcpy(eedf, I.eedf, 8 * (size_t)I.eedf_bins, hipMemcpyDeviceToHost));
   (void)sl;
+  return status_of(S.status);
+}
+
+pic_status pic_moments(pic_ctx *c, int32_t inst, int32_t species, double *ux, double *tx, double *power) {
+  pic_status r = check_inst(c, inst);
+  if (r != PIC_OK) return r;
+  const InstDev &I = c->host_inst[inst];
+  if (species < 0 || species >= I.nsp) return fail(c, PIC_EINVAL, "species out of range");
+  InstState S;
+  r = read_state(c, inst, S);
+  if (r != PIC_OK) return r;
+  const size_t n1 = (size_t)I.N + 1, N = (size_t)I.N;
+  std::vector<double> a(n1), m1(n1), m2(n1), p(N), h(N);
+  HIP_TRY(c, hipMemcpy(a.data(), I.accA[species], 8 * n1, hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(m1.data(), I.accM1[species], 8 * n1, hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(m2.data(), I.accM2[species], 8 * n1, hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(p.data(), I.accP[species], 8 * N, hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(h.data(), I.h, 8 * N, hipMemcpyDeviceToHost));
+  if (I.bc == PIC_BC_PERIODIC) {   // node N is node 0 (the deposit is folded the same way)
+    m1[0] += m1[N];
+    m1[N] = m1[0];
+    m2[0] += m2[N];
+    m2[N] = m2[0];
+  }
+  const double mq = I.mass[species] / kQE;
+  for (size_t n = 0; n < n1; ++n) {
+    const double w = a[n] * 0x1p-32;   // sum of the particles' weights at node n
+    const double u = w > 0.0 ? m1[n] / w : 0.0;
+    if (ux) ux[n] = u;
+    if (tx) tx[n] = w > 0.0 ? mq * (m2[n] / w - u * u) : 0.0;
+  }
+  const double ns = (double)std::max(S.n_samples, 1);
+  if (power)
+    for (size_t j = 0; j < N; ++j) power[j] = (I.qW[species] * p[j]) / (h[j] * ns);
   return status_of(S.status);
 }
 

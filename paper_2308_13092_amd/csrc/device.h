@@ -84,6 +84,8 @@ struct InstDev {
   double *accA[2], *acc_phi;
   unsigned long long *eedf;
   unsigned long long *impact;  // [species][wall][energy bins + 1 | angle bins]
+  double *accM1[2], *accM2[2];  // averaged sum w vx, sum w vx^2 per node (CIC weights)
+  double *accP[2];              // averaged sum vx E(x) per cell
   int32_t imp_bins, imp_abins;
   double imp_escale, imp_ascale;  // bins / emax (1/eV), angle bins / 90 (1/deg)
   unsigned long long *scount[2], *scursor[2];

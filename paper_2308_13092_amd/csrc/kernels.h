@@ -28,6 +28,9 @@ hipError_t launch_sort(const InstDev *insts, InstState *states, int n_inst, int 
 void launch_diag(const InstDev *insts, InstState *states, int inst, int prec,
                  unsigned long long *out, hipStream_t s);
 void launch_zero_deposit(const InstDev *insts, InstState *states, int n_inst, hipStream_t s);
+// Velocity moments and power of the discharges whose averaging is due.
+void launch_moments(const InstDev *insts, InstState *states, int n_inst, int prec, int grid, int max_n,
+                    hipStream_t s);
 
 // Diagnostics reduction output layout (unsigned long long words).
 enum : int { D_LIVE0 = 0, D_LIVE1 = 1, D_KE0 = 2, D_KE1 = 3, D_VMAX = 4, D_NWORDS = 8 };

@@ -1244,6 +1244,121 @@ k_diag(const InstDev *__restrict__ insts, const InstState *__restrict__ states, 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Velocity moments and power of the averaged profiles (Section 3a), on the
+// averaged steps, from x^k, v^{k-1/2} and E^k (before the push).  Per node,
+// with linear (CIC) weights in FP64: sum w vx and sum w vx^2; per cell, the
+// power given to the particles in it, sum vx E(x), E(x) being the gathered
+// field (E_j for EC, linear for MC).  FP64 sums: their order, and so their
+// last bits, may differ from run to run.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool avg_due(CInst &I, int64_t k) {
+  return I.avg_every > 0 && k >= I.avg_start && ((k - I.avg_start) % I.avg_every) == 0;
+}
+
+template <class F>
+__global__ void __launch_bounds__(256)
+k_moments(const InstDev *__restrict__ insts, const InstState *__restrict__ states, int n_inst,
+          int max_n) {
+  constexpr int BLOCK = 256, TILE = BLOCK * 4;
+  __shared__ int prefix[2 * kMaxInst + 1];
+  extern __shared__ __align__(16) unsigned char dsm[];
+  const int np1 = max_n + 1;
+  double *m1 = reinterpret_cast<double *>(dsm);
+  double *m2 = m1 + np1;
+  double *pw = m2 + np1;
+  double *sE = pw + max_n;
+  double *sNodes = sE + np1;   // FP64 form only
+  const int t = threadIdx.x;
+  const int nseg = 2 * n_inst;
+  for (int j = t; j < np1; j += BLOCK) { m1[j] = 0.0; m2[j] = 0.0; }
+  for (int j = t; j < max_n; j += BLOCK) pw[j] = 0.0;
+  for (int s = t; s < nseg; s += BLOCK) {
+    CInst &I = cinst(insts)[s >> 1];
+    const InstState &S = states[s >> 1];
+    const bool ok = I.active && S.frozen == 0 && (s & 1) < I.nsp &&
+                    !(I.k_stop > 0 && S.k >= I.k_stop) && avg_due(I, S.k);
+    prefix[s + 1] = ok ? (int)((S.extent[s & 1] + TILE - 1) / TILE) : 0;
+  }
+  if (t == 0) prefix[0] = 0;
+  __syncthreads();
+  if (t == 0)
+    for (int s = 1; s <= nseg; ++s) prefix[s] += prefix[s - 1];
+  __syncthreads();
+  const int64_t T = prefix[nseg];
+  const int64_t t0 = T * blockIdx.x / gridDim.x, t1 = T * (blockIdx.x + 1) / gridDim.x;
+  int seg = -1, N = 0, gather = 0;
+  CInst *Ip = nullptr;
+  int64_t ext = 0;
+  typename F::View P;
+  GridPar G{0, 0, 0, 0.0};
+  auto flush = [&]() {
+    __syncthreads();
+    CInst &I = *Ip;
+    const int sp = seg & 1;
+    for (int n = t; n <= N; n += BLOCK) {
+      if (m1[n] != 0.0) atomicAdd(&I.accM1[sp][n], m1[n]);
+      if (m2[n] != 0.0) atomicAdd(&I.accM2[sp][n], m2[n]);
+      m1[n] = 0.0;
+      m2[n] = 0.0;
+      if (n < N) {
+        if (pw[n] != 0.0) atomicAdd(&I.accP[sp][n], pw[n]);
+        pw[n] = 0.0;
+      }
+    }
+    __syncthreads();
+  };
+  for (int64_t tile = t0; tile < t1; ++tile) {
+    int s = seg < 0 ? 0 : seg;
+    while (prefix[s + 1] <= tile) ++s;
+    s = __builtin_amdgcn_readfirstlane(s);
+    if (s != seg) {
+      if (seg >= 0) flush();
+      seg = s;
+      Ip = &cinst(insts)[seg >> 1];
+      CInst &I = *Ip;
+      const InstState &S = states[seg >> 1];
+      N = I.N;
+      gather = I.gather;
+      G = grid_par(I);
+      ext = S.extent[seg & 1];
+      P = F::view(I, seg & 1, S.parity);
+      const int ne = (gather == 0) ? N : N + 1;
+      for (int j = t; j < ne; j += BLOCK) sE[j] = I.E64[j];
+      if (F::prec == 0 && !I.uniform)
+        for (int j = t; j <= N; j += BLOCK) sNodes[j] = I.nodes[j];
+      __syncthreads();
+    }
+    const int64_t base = (tile - prefix[seg]) * TILE;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t i = base + q * BLOCK + t;
+      if (i >= ext) continue;
+      int j;
+      double xi, vx;
+      if constexpr (F::prec == 1) {
+        j = P.cell[i];
+        if (j < 0) continue;
+        xi = (double)P.off[i];
+        vx = (double)P.vx[i];
+      } else {
+        const double x = P.x[i];
+        if (!(x >= 0.0)) continue;
+        j = locate64(G, sNodes, x, xi);
+        vx = P.vx[i];
+      }
+      const double w0 = 1.0 - xi, w1 = xi;
+      atomicAdd(&m1[j], w0 * vx);
+      atomicAdd(&m1[j + 1], w1 * vx);
+      atomicAdd(&m2[j], w0 * (vx * vx));
+      atomicAdd(&m2[j + 1], w1 * (vx * vx));
+      const double e = (gather == 0) ? sE[j] : (1.0 - xi) * sE[j] + xi * sE[j + 1];
+      atomicAdd(&pw[j], vx * e);
+    }
+  }
+  if (seg >= 0) flush();
+}
+
 __global__ void k_zero_deposit(const InstDev *__restrict__ insts, const InstState *__restrict__ states) {
   CInst &I = cinst(insts)[blockIdx.x];
   const InstState &S = states[blockIdx.x];
@@ -1345,6 +1460,16 @@ void launch_diag(const InstDev *insts, InstState *states, int inst, int prec,
     hipLaunchKernelGGL(k_diag<F32>, dim3(1024), dim3(256), 0, s, insts, states, inst, out);
   else
     hipLaunchKernelGGL(k_diag<F64>, dim3(1024), dim3(256), 0, s, insts, states, inst, out);
+}
+
+void launch_moments(const InstDev *insts, InstState *states, int n_inst, int prec, int grid, int max_n,
+                    hipStream_t s) {
+  const size_t np1 = (size_t)max_n + 1;
+  const size_t lds = 8 * (np1 * 3 + (size_t)max_n + (prec == 0 ? np1 : 0));
+  if (prec == 1)
+    hipLaunchKernelGGL(k_moments<F32>, dim3(grid), dim3(256), lds, s, insts, states, n_inst, max_n);
+  else
+    hipLaunchKernelGGL(k_moments<F64>, dim3(grid), dim3(256), lds, s, insts, states, n_inst, max_n);
 }
 
 void launch_zero_deposit(const InstDev *insts, InstState *states, int n_inst, hipStream_t s) {

@@ -276,3 +276,23 @@ def test_impact_distributions_against_oracle(gpu, prec):
             da = np.abs(h["angle"] - ref.impact_a[s, w]).sum()
             note("impact", s, w, int(ref.absorbed[s, w]), int(de), int(da))
             assert de <= 4 + tot // 50 and da <= 4 + tot // 50
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("kind", ["uniform", "refined", "periodic"])
+@pytest.mark.parametrize("gather", [0, 1])
+def test_moments_against_oracle(gpu, prec, kind, gather):
+    """Averaged velocity moments and power after one step from identical
+    state (sampled before the push): FP64 sums in different orders."""
+    note("moments", prec, kind, gather)
+    cfg = case_cfg(prec, kind, gather=gather, avg_every=1)
+    states = case_states(cfg)
+    ref = oracle_from_states(cfg, states, K0)
+    ctx = gpu_from_states(cfg, states, K0, Context())
+    ctx.step(1)
+    ref.step()
+    for s in range(2):
+        g = ctx.moments(0, s)
+        r = ref.moments(s)
+        for key in ("ux", "tx", "power"):
+            assert normwise(g[key], r[key]) <= 1e-10, (s, key, normwise(g[key], r[key]))
