@@ -115,10 +115,12 @@ def test_graph_replay_equals_eager_launches(gpu, prec):
         assert_same_instance(a, i, b, i)
 
 
+@pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("block,bpc", [(256, 1), (1024, 0), (512, 5)])
-def test_launch_shape_does_not_change_results(gpu, block, bpc):
-    cfgs = [c for c in mixed_configs(1) if c["n_cells"] > 0][:3]
-    note("launch shape", block, bpc)
+def test_launch_shape_does_not_change_results(gpu, block, bpc, prec):
+    """Small tiles split every species over several workgroups."""
+    cfgs = [c for c in mixed_configs(prec) if c["n_cells"] > 0][:3]
+    note("launch shape", block, bpc, prec)
     a, b = Context()(cfgs), Context()(cfgs)
     b.set_tuning(block=block, blocks_per_cu=bpc, sort_interval=7)
     a.step(33)
