@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define PIC_ABI_VERSION 2
+#define PIC_ABI_VERSION 3
 
 typedef struct pic_ctx pic_ctx;  /* opaque; owns host-side metadata only */
 
@@ -109,6 +109,10 @@ typedef struct pic_config {
   int32_t impact_angle_bins; /* bins of the angle to the wall normal over [0, 90] deg
                                 (<= PIC_MAX_EEDF_BINS); 0 -> 90                        */
   double impact_emax_ev;     /* 0 -> 1000 eV                                           */
+  /* 1: also accumulate the velocity moments and power of pic_moments on the
+     averaged steps (an extra pass over the particles on each of them);
+     0: off. */
+  int32_t moments;
 } pic_config;
 
 #define PIC_MAX_CELLS 2048
@@ -256,7 +260,8 @@ pic_status pic_profiles(pic_ctx *ctx, int32_t inst, double *ne, double *ni, doub
  * tx = (m/e)(sum w vx^2 / sum w - ux^2) (eV), w the particles' linear
  * weights; per cell the power density given to the species,
  * q W sum_{p in cell j} vx_p E(x_p) / h_j averaged over the samples (W/m^3,
- * E(x) the gathered field).  Any pointer may be NULL.  Synchronises. */
+ * E(x) the gathered field).  Any pointer may be NULL.  Synchronises.
+ * PIC_ESTATE when the instance was configured with moments = 0. */
 pic_status pic_moments(pic_ctx *ctx, int32_t inst, int32_t species, double *ux, double *tx,
                        double *power);
 

@@ -32,6 +32,7 @@ DEFAULTS = dict(
     gamma_see=0.0, t_see_ev=2.0, seed=1, n_species=2, collisions=1, pullback=0,
     nu_max_e=0.0, nu_max_i=0.0, avg_start=0, avg_every=0, eedf_every=0, eedf_bins=200,
     eedf_emax_ev=50.0, eedf_width_m=1e-3, impact_bins=0, impact_angle_bins=0, impact_emax_ev=0.0,
+    moments=0,
 )
 
 
@@ -163,7 +164,8 @@ class Sim:
         if c["avg_every"] > 0 and k >= c["avg_start"] and (k - c["avg_start"]) % c["avg_every"] == 0:
             for s in range(self.nsp):
                 self.acc_A[s] += self.A[s].astype(np.float64)
-                self._accumulate_moments(s)
+                if c["moments"]:
+                    self._accumulate_moments(s)
             self.acc_phi += self.phi
             self.n_samples += 1
 

@@ -34,6 +34,7 @@ class pic_config(C.Structure):
         ("eedf_every", C.c_int32), ("eedf_bins", C.c_int32), ("eedf_emax_ev", C.c_double),
         ("eedf_width_m", C.c_double), ("k_stop", C.c_int64), ("growth_limit", C.c_double),
         ("impact_bins", C.c_int32), ("impact_angle_bins", C.c_int32), ("impact_emax_ev", C.c_double),
+        ("moments", C.c_int32),
     ]
 
 

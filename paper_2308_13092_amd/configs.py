@@ -38,7 +38,7 @@ def base(**over):
                precision=0, gamma_see=0.1, t_see_ev=2.0, seed=1, sort_interval=50, n_species=2,
                collisions=1, pullback=0, nu_max_e=0.0, nu_max_i=0.0, avg_start=0, avg_every=0,
                eedf_every=0, eedf_bins=200, eedf_emax_ev=50.0, eedf_width_m=1e-3, k_stop=0,
-               growth_limit=0.0)
+               growth_limit=0.0, moments=0)
     cfg.update(over)
     return cfg
 

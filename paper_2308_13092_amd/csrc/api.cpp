@@ -429,6 +429,7 @@ static pic_status setup_slot(pic_ctx *c, int i, const pic_config &cfg) {
   I.imp_abins = eff_abins(cfg);
   I.imp_escale = (double)I.imp_bins / (cfg.impact_emax_ev > 0.0 ? cfg.impact_emax_ev : 1000.0);
   I.imp_ascale = (double)I.imp_abins / 90.0;
+  I.moments = cfg.moments ? 1 : 0;
   for (int s = 0; s < 2; ++s) {
     I.scount[s] = (unsigned long long *)(base + g.scount[s]);
     I.scursor[s] = (unsigned long long *)(base + g.scursor[s]);
@@ -553,7 +554,7 @@ static pic_status ev_end(pic_ctx *c) {
 // Whether any slot accumulates averaged profiles (the moments kernel runs).
 static bool any_averaging(const pic_ctx *c) {
   for (int i = 0; i < c->n_inst; ++i)
-    if (c->slots[i].used && c->host_inst[i].avg_every > 0) return true;
+    if (c->slots[i].used && c->host_inst[i].avg_every > 0 && c->host_inst[i].moments) return true;
   return false;
 }
 
@@ -1070,6 +1071,7 @@ pic_status pic_moments(pic_ctx *c, int32_t inst, int32_t species, double *ux, do
   if (r != PIC_OK) return r;
   const InstDev &I = c->host_inst[inst];
   if (species < 0 || species >= I.nsp) return fail(c, PIC_EINVAL, "species out of range");
+  if (!I.moments) return fail(c, PIC_ESTATE, "moments were not enabled for this instance");
   InstState S;
   r = read_state(c, inst, S);
   if (r != PIC_OK) return r;

@@ -88,6 +88,7 @@ struct InstDev {
   double *accP[2];              // averaged sum vx E(x) per cell
   int32_t imp_bins, imp_abins;
   double imp_escale, imp_ascale;  // bins / emax (1/eV), angle bins / 90 (1/deg)
+  int moments;                    // accumulate accM1, accM2, accP on the averaged steps
   unsigned long long *scount[2], *scursor[2];
   int *queue[2];               // per-species queue of particles for the drain kernel
   // particles

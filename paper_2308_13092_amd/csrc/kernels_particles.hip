@@ -1256,6 +1256,12 @@ __device__ __forceinline__ bool avg_due(CInst &I, int64_t k) {
   return I.avg_every > 0 && k >= I.avg_start && ((k - I.avg_start) % I.avg_every) == 0;
 }
 
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 template <class F>
 __global__ void __launch_bounds__(256)
 k_moments(const InstDev *__restrict__ insts, const InstState *__restrict__ states, int n_inst,
@@ -1269,7 +1275,7 @@ k_moments(const InstDev *__restrict__ insts, const InstState *__restrict__ state
   double *pw = m2 + np1;
   double *sE = pw + max_n;
   double *sNodes = sE + np1;   // FP64 form only
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, lane = __lane_id();
   const int nseg = 2 * n_inst;
   for (int j = t; j < np1; j += BLOCK) { m1[j] = 0.0; m2[j] = 0.0; }
   for (int j = t; j < max_n; j += BLOCK) pw[j] = 0.0;
@@ -1277,7 +1283,7 @@ k_moments(const InstDev *__restrict__ insts, const InstState *__restrict__ state
     CInst &I = cinst(insts)[s >> 1];
     const InstState &S = states[s >> 1];
     const bool ok = I.active && S.frozen == 0 && (s & 1) < I.nsp &&
-                    !(I.k_stop > 0 && S.k >= I.k_stop) && avg_due(I, S.k);
+                    !(I.k_stop > 0 && S.k >= I.k_stop) && I.moments && avg_due(I, S.k);
     prefix[s + 1] = ok ? (int)((S.extent[s & 1] + TILE - 1) / TILE) : 0;
   }
   if (t == 0) prefix[0] = 0;
@@ -1333,27 +1339,62 @@ k_moments(const InstDev *__restrict__ insts, const InstState *__restrict__ state
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int64_t i = base + q * BLOCK + t;
-      if (i >= ext) continue;
-      int j;
-      double xi, vx;
-      if constexpr (F::prec == 1) {
-        j = P.cell[i];
-        if (j < 0) continue;
-        xi = (double)P.off[i];
-        vx = (double)P.vx[i];
-      } else {
-        const double x = P.x[i];
-        if (!(x >= 0.0)) continue;
-        j = locate64(G, sNodes, x, xi);
-        vx = P.vx[i];
+      bool ok = i < ext;
+      int j = 0;
+      double xi = 0.0, vx = 0.0;
+      if (ok) {
+        if constexpr (F::prec == 1) {
+          j = P.cell[i];
+          ok = j >= 0;
+          if (ok) {
+            xi = (double)P.off[i];
+            vx = (double)P.vx[i];
+          }
+        } else {
+          const double x = P.x[i];
+          ok = x >= 0.0;
+          if (ok) {
+            j = locate64(G, sNodes, x, xi);
+            vx = P.vx[i];
+          }
+        }
       }
-      const double w0 = 1.0 - xi, w1 = xi;
-      atomicAdd(&m1[j], w0 * vx);
-      atomicAdd(&m1[j + 1], w1 * vx);
-      atomicAdd(&m2[j], w0 * (vx * vx));
-      atomicAdd(&m2[j + 1], w1 * (vx * vx));
-      const double e = (gather == 0) ? sE[j] : (1.0 - xi) * sE[j] + xi * sE[j + 1];
-      atomicAdd(&pw[j], vx * e);
+      double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0, pp = 0.0;
+      if (ok) {
+        const double w0 = 1.0 - xi, w1 = xi;
+        a0 = w0 * vx;
+        a1 = w1 * vx;
+        b0 = w0 * (vx * vx);
+        b1 = w1 * (vx * vx);
+        const double e = (gather == 0) ? sE[j] : (1.0 - xi) * sE[j] + xi * sE[j + 1];
+        pp = vx * e;
+      }
+      // A cell-sorted state puts whole wavefronts in one cell: then the
+      // wavefront sums its terms and one lane adds them (same-address LDS
+      // atomics would serialise); otherwise every lane adds its own.
+      const unsigned long long act = __ballot(ok);
+      if (act == 0) continue;
+      const int j0 = __shfl(j, __ffsll((long long)act) - 1, 64);
+      if (__ballot(ok && j != j0) == 0) {
+        a0 = wave_sum_f64(a0);
+        a1 = wave_sum_f64(a1);
+        b0 = wave_sum_f64(b0);
+        b1 = wave_sum_f64(b1);
+        pp = wave_sum_f64(pp);
+        if (lane == 0) {
+          atomicAdd(&m1[j0], a0);
+          atomicAdd(&m1[j0 + 1], a1);
+          atomicAdd(&m2[j0], b0);
+          atomicAdd(&m2[j0 + 1], b1);
+          atomicAdd(&pw[j0], pp);
+        }
+      } else if (ok) {
+        atomicAdd(&m1[j], a0);
+        atomicAdd(&m1[j + 1], a1);
+        atomicAdd(&m2[j], b0);
+        atomicAdd(&m2[j + 1], b1);
+        atomicAdd(&pw[j], pp);
+      }
     }
   }
   if (seg >= 0) flush();

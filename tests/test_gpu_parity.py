@@ -285,7 +285,7 @@ def test_moments_against_oracle(gpu, prec, kind, gather):
     """Averaged velocity moments and power after one step from identical
     state (sampled before the push): FP64 sums in different orders."""
     note("moments", prec, kind, gather)
-    cfg = case_cfg(prec, kind, gather=gather, avg_every=1)
+    cfg = case_cfg(prec, kind, gather=gather, avg_every=1, moments=1)
     states = case_states(cfg)
     ref = oracle_from_states(cfg, states, K0)
     ctx = gpu_from_states(cfg, states, K0, Context())
@@ -296,3 +296,24 @@ def test_moments_against_oracle(gpu, prec, kind, gather):
         r = ref.moments(s)
         for key in ("ux", "tx", "power"):
             assert normwise(g[key], r[key]) <= 1e-10, (s, key, normwise(g[key], r[key]))
+
+
+def test_moments_are_opt_in(gpu):
+    """Without moments = 1 nothing is accumulated and pic_moments says so;
+    the step itself is unchanged."""
+    import paper_2308_13092_amd._lib as L
+    note("moments off")
+    cfg = case_cfg(1, "uniform", avg_every=1)
+    states = case_states(cfg)
+    a = gpu_from_states(cfg, states, K0, Context())
+    b = gpu_from_states(dict(cfg, moments=1), states, K0, Context())
+    a.step(3)
+    b.step(3)
+    with pytest.raises(L.PicError) as e:
+        a.moments(0, 0)
+    assert e.value.status == L.PIC_ESTATE
+    for s in range(2):
+        sa, sb = a.get_state(0, s), b.get_state(0, s)
+        oa, ob = np.argsort(sa["id"]), np.argsort(sb["id"])   # storage order is unspecified
+        for key in sa:
+            assert np.array_equal(sa[key][oa], sb[key][ob]), (s, key)

@@ -21,7 +21,7 @@ def sp_at(s, x, vx, vy=None):
 def test_two_particles_on_a_node_give_their_mean_and_spread():
     u, a = 2.0e5, 3.0e5
     cfg = inputs.small_discharge(n_cells=8, gap_m=8.0, bc=1, n_species=1, v_rf=0.0, collisions=0,
-                                 weight_m2=1e-9, avg_every=1)
+                                 weight_m2=1e-9, avg_every=1, moments=1)
     sim = Sim(cfg, species=[sp_at(0, [3.0, 3.0], [u - a, u + a])])
     sim.step()
     m = sim.moments(0)
@@ -37,7 +37,7 @@ def test_power_in_a_uniform_field():
     V, L, N = 100.0, 0.08, 16
     W = 1e-3
     cfg = inputs.small_discharge(n_cells=N, gap_m=L, v_rf=V, phase=math.pi / 2, collisions=0,
-                                 weight_m2=W, avg_every=1)
+                                 weight_m2=W, avg_every=1, moments=1)
     ve, vi = 3.0e5, -2.0e3
     sim = Sim(cfg, species=[sp_at(0, [0.0123], [ve]), sp_at(1, [0.0567], [vi])])
     sim.step()
@@ -60,7 +60,7 @@ def test_drifting_maxwellian():
     x = g.uniform(0.0, L, n)
     vx = u + sig * g.standard_normal(n)
     cfg = inputs.small_discharge(n_cells=N, gap_m=L, bc=1, n_species=1, v_rf=0.0, collisions=0,
-                                 n0_m3=1e6, avg_every=1)
+                                 n0_m3=1e6, avg_every=1, moments=1)
     sim = Sim(cfg, species=[sp_at(0, x, vx)])
     sim.step()
     m = sim.moments(0)
