@@ -32,6 +32,12 @@ silent the reading taken is stated in the docstring; the readings are:
   the same wall with probability gamma.
 * FP32-state form: the particle keeps an int32 cell and an FP32 offset; the
   push moves it by an FP32 cell walk whose operation order is fixed below.
+* Second-order EC (Section 2a: the gather shape one order below the deposit
+  shape), uniform grids only: quadratic-spline (S2) deposit to the nearest
+  node and its two neighbours, linear (S1) gather of the cell-centred field.
+  Deposit weights that fall beyond a Dirichlet end go to the electrode node;
+  the matching gather sees a zero field half a cell outside each electrode.
+  A periodic grid wraps both.
 """
 from __future__ import annotations
 
@@ -49,7 +55,7 @@ INT32_MAX = 2 ** 31 - 1
 TWO_PI = 2.0 * math.pi
 
 BC_DIRICHLET, BC_PERIODIC = 0, 1
-GATHER_EC, GATHER_MC = 0, 1
+GATHER_EC, GATHER_MC, GATHER_EC2 = 0, 1, 2
 FP64, FP32 = 0, 1
 
 # Philox counter tags (counter word 1 = tag | species << 8).
@@ -259,8 +265,45 @@ def weights(xi):
     return w0, w1
 
 
-def deposit_species(grid: Grid, sp: Species):
-    """A_{s,n} = sum over particles of the S1 weights of node n (int64, exact)."""
+def weights_s2(j, xi):
+    """Fixed-point quadratic-spline (S2) weights of a particle at (j, xi).
+
+    The particle's nearest node is n = j (xi < 1/2) or j + 1, at signed
+    distance d = xi or xi - 1 cells.  The spline gives nodes n-1, n, n+1 the
+    weights (1/2 - d)^2/2, 3/4 - d^2, (1/2 + d)^2/2.  With a = 1/2 - d and
+    b = 1/2 + d formed in FP64 (a = 1/2 - xi or 3/2 - xi, b = 1/2 + xi or
+    xi - 1/2), wl = rint(a a 2^31), wr = rint(b b 2^31) (half-to-even) and
+    wc = 2^32 - wl - wr, so the three sum to 2^32 exactly.
+    Returns (n, wl, wc, wr).
+    """
+    j = np.asarray(j, dtype=np.int64)
+    xi = np.asarray(xi, dtype=np.float64)
+    up = xi >= 0.5
+    n = j + up.astype(np.int64)
+    a = np.where(up, 1.5 - xi, 0.5 - xi)
+    b = np.where(up, xi - 0.5, 0.5 + xi)
+    wl = np.rint((a * a) * 2147483648.0).astype(np.int64)
+    wr = np.rint((b * b) * 2147483648.0).astype(np.int64)
+    wc = (np.int64(1) << np.int64(32)) - wl - wr
+    return n, wl, wc, wr
+
+
+def fold_s2(grid: Grid, m):
+    """Node index of an S2 weight at node m in [-1, N+1]: beyond a Dirichlet
+    end it goes to the electrode node; a periodic grid wraps it."""
+    N = grid.N
+    m = np.asarray(m, dtype=np.int64).copy()
+    if grid.bc == BC_PERIODIC:
+        m[m < 0] += N
+        m[m > N] -= N
+    else:
+        m = np.clip(m, 0, N)
+    return m
+
+
+def deposit_species(grid: Grid, sp: Species, gather=GATHER_EC):
+    """A_{s,n} = sum over particles of the weights of node n (int64, exact):
+    S1 for EC and MC, S2 for second-order EC."""
     A = np.zeros(grid.N + 1, dtype=np.int64)
     if sp.n == 0:
         return A
@@ -269,9 +312,15 @@ def deposit_species(grid: Grid, sp: Species):
     else:
         j = sp.cell.astype(np.int64)
         xi = sp.off.astype(np.float64)
-    w0, w1 = weights(xi)
-    np.add.at(A, j, w0)
-    np.add.at(A, j + 1, w1)
+    if gather == GATHER_EC2:
+        n, wl, wc, wr = weights_s2(j, xi)
+        np.add.at(A, fold_s2(grid, n - 1), wl)
+        np.add.at(A, n, wc)
+        np.add.at(A, fold_s2(grid, n + 1), wr)
+    else:
+        w0, w1 = weights(xi)
+        np.add.at(A, j, w0)
+        np.add.at(A, j + 1, w1)
     if grid.bc == BC_PERIODIC:
         A[0] += A[grid.N]
         A[grid.N] = A[0]
@@ -384,22 +433,60 @@ def field_mc(grid: Grid, phi, Q):
     return E
 
 
+def field_ec2(grid: Grid, phi):
+    """Gather table of second-order EC: the cell fields E_j of Eq (5) at the
+    cell centres, with one ghost centre outside each end, N + 2 values
+    G[m] = E_{m-1}.  The ghosts follow from the folded S2 deposit (the
+    particle's energy sum_n S2_n(x) phi_n with the outside weight on the
+    electrode node is that of a ghost node at the electrode's potential):
+    zero field at a Dirichlet end, the wrapped cell in a periodic box."""
+    E = field_ec(grid, phi)
+    N = grid.N
+    G = np.zeros(N + 2)
+    G[1:N + 1] = E
+    if grid.bc == BC_PERIODIC:
+        G[0] = E[N - 1]
+        G[N + 1] = E[0]
+    return G
+
+
 # ---------------------------------------------------------------------------
 # Steps 4-5: gather and leapfrog push (Eqs 6-9)
 # ---------------------------------------------------------------------------
+def s2_gather_index(j, xi):
+    """Second-order EC gather of a particle at (j, xi): linear between the
+    two cell centres around it, table entries m and m + 1 (G[m] = E_{m-1}),
+    m = j with t = xi + 1/2 when xi < 1/2, else m = j + 1 with t = xi - 1/2."""
+    up = xi >= 0.5
+    m = j + up.astype(np.int64)
+    t = np.where(up, xi - 0.5, xi + 0.5)
+    return m, t
+
+
 def gather_fp64(grid: Grid, x, E, gather):
     j, xi = locate(grid, x)
     if gather == GATHER_EC:
         return E[j]
+    if gather == GATHER_EC2:
+        m, t = s2_gather_index(j, xi)
+        return (1.0 - t) * E[m] + t * E[m + 1]
     return (1.0 - xi) * E[j] + xi * E[j + 1]
 
 
 def gather_fp32(cell, off, E32, gather):
-    """FP32 gather: EC takes E32[cell]; MC forms ((1 - off) E_j) + (off E_{j+1}) in FP32."""
+    """FP32 gather: EC takes E32[cell]; MC forms ((1 - off) E_j) + (off E_{j+1})
+    in FP32; second-order EC forms t = off + 1/2 or off - 1/2 in FP32, then
+    ((1 - t) G_m) + (t G_{m+1})."""
     j = cell.astype(np.int64)
     if gather == GATHER_EC:
         return E32[j]
     one = np.float32(1.0)
+    if gather == GATHER_EC2:
+        half = np.float32(0.5)
+        up = off >= half
+        m = j + up.astype(np.int64)
+        t = np.where(up, off - half, off + half).astype(np.float32)
+        return ((one - t) * E32[m]) + (t * E32[m + 1])
     a = (one - off) * E32[j]
     b = off * E32[j + 1]
     return a + b

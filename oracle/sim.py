@@ -20,10 +20,11 @@ import math
 import numpy as np
 
 from . import physics as ph
-from .pic import (BC_PERIODIC, FP64, GATHER_EC, TAG_CHILD, TWO_M32, Grid, MccCounts, Species,
-                  collide_electrons, collide_ions, deposit_species, draw, emit_secondaries,
-                  field_ec, field_mc, gas_velocity, gather_fp32, gather_fp64, ids_from_words,
-                  init_species, locate, next_candidate, node_charge, poisson, push_fp32, push_fp64)
+from .pic import (BC_PERIODIC, FP64, GATHER_EC, GATHER_EC2, TAG_CHILD, TWO_M32, Grid, MccCounts,
+                  Species, collide_electrons, collide_ions, deposit_species, draw, emit_secondaries,
+                  field_ec, field_ec2, field_mc, fold_s2, gas_velocity, gather_fp32, gather_fp64,
+                  ids_from_words, init_species, locate, next_candidate, node_charge, poisson,
+                  push_fp32, push_fp64, s2_gather_index)
 
 DEFAULTS = dict(
     n_cells=128, bc=0, nodes=None, gap_m=0.025, v_rf=200.0, f_rf=13.56e6, phase=0.0,
@@ -69,6 +70,8 @@ class Sim:
         self.dt = float(c["dt_s"])
         self.prec = int(c["precision"])
         self.gather = int(c["gather"])
+        if self.gather == GATHER_EC2 and not g.uniform:
+            raise ValueError("second-order EC needs a uniform grid")
         self.nsp = int(c["n_species"])
         W = float(c["weight_m2"])
         if W == 0.0:
@@ -127,7 +130,7 @@ class Sim:
 
     # -- steps 1-3 --------------------------------------------------------
     def deposit(self):
-        self.A = [deposit_species(self.grid, sp) for sp in self.sp]
+        self.A = [deposit_species(self.grid, sp, self.gather) for sp in self.sp]
         return self.A
 
     def solve(self):
@@ -138,6 +141,8 @@ class Sim:
         self.E_cell = field_ec(self.grid, self.phi)
         if self.gather == GATHER_EC:
             self.E = self.E_cell
+        elif self.gather == GATHER_EC2:
+            self.E = field_ec2(self.grid, self.phi)
         else:
             self.E = field_mc(self.grid, self.phi, self.Q)
         self.field_energy = 0.5 * ph.EPS0 * float(np.sum(self.grid.h * self.E_cell * self.E_cell))
@@ -171,8 +176,9 @@ class Sim:
 
     def _accumulate_moments(self, s):
         """Section 3a moments from x^k, v^{k-1/2} and E^k: sum w vx and
-        sum w vx^2 at the nodes with the linear weights w = 1 - xi, xi, and per
-        cell sum vx E(x) with the gathered field (E_j for EC, linear for MC)."""
+        sum w vx^2 at the nodes with the deposit's shape (linear weights
+        w = 1 - xi, xi; for second-order EC the quadratic spline, in FP64),
+        and per cell sum vx E(x) with the gathered field."""
         sp = self.sp[s]
         if sp.n == 0:
             return
@@ -182,13 +188,27 @@ class Sim:
             j = sp.cell.astype(np.int64)
             xi = sp.off.astype(np.float64)
         vx = sp.vx.astype(np.float64)
-        w0, w1 = 1.0 - xi, xi
-        np.add.at(self.acc_m1[s], j, w0 * vx)
-        np.add.at(self.acc_m1[s], j + 1, w1 * vx)
-        np.add.at(self.acc_m2[s], j, w0 * (vx * vx))
-        np.add.at(self.acc_m2[s], j + 1, w1 * (vx * vx))
         E = self.E
-        e = E[j] if self.gather == GATHER_EC else (1.0 - xi) * E[j] + xi * E[j + 1]
+        if self.gather == GATHER_EC2:
+            up = xi >= 0.5
+            n = j + up.astype(np.int64)
+            a = np.where(up, 1.5 - xi, 0.5 - xi)
+            b = np.where(up, xi - 0.5, 0.5 + xi)
+            wl = 0.5 * (a * a)
+            wr = 0.5 * (b * b)
+            wc = 1.0 - wl - wr
+            for idx, w in ((fold_s2(self.grid, n - 1), wl), (n, wc), (fold_s2(self.grid, n + 1), wr)):
+                np.add.at(self.acc_m1[s], idx, w * vx)
+                np.add.at(self.acc_m2[s], idx, w * (vx * vx))
+            m, t = s2_gather_index(j, xi)
+            e = (1.0 - t) * E[m] + t * E[m + 1]
+        else:
+            w0, w1 = 1.0 - xi, xi
+            np.add.at(self.acc_m1[s], j, w0 * vx)
+            np.add.at(self.acc_m1[s], j + 1, w1 * vx)
+            np.add.at(self.acc_m2[s], j, w0 * (vx * vx))
+            np.add.at(self.acc_m2[s], j + 1, w1 * (vx * vx))
+            e = E[j] if self.gather == GATHER_EC else (1.0 - xi) * E[j] + xi * E[j + 1]
         np.add.at(self.acc_p[s], j, vx * e)
 
     def moments(self, s):
