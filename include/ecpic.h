@@ -6,7 +6,9 @@
  * particle-in-cell loop of Powis & Kaganovich (Section 2a: charge deposit,
  * Poisson solve, cell-centred field, offset nearest-grid-point gather,
  * leapfrog push, Monte-Carlo collisions), with the momentum-conserving
- * centred field and linear gather selectable per instance.
+ * centred field and linear gather, or a second-order energy-conserving pair
+ * (quadratic-spline deposit, linear gather of the cell field: the gather
+ * shape one order below the deposit's, Section 2a), selectable per instance.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -57,7 +59,7 @@ typedef enum {
 } pic_status;
 
 enum { PIC_BC_DIRICHLET_RF = 0, PIC_BC_PERIODIC = 1 };
-enum { PIC_GATHER_EC = 0, PIC_GATHER_MC = 1 };
+enum { PIC_GATHER_EC = 0, PIC_GATHER_MC = 1, PIC_GATHER_EC2 = 2 };
 enum { PIC_FP64 = 0, PIC_FP32_STATE = 1 };
 
 /*
@@ -80,7 +82,11 @@ typedef struct pic_config {
   int64_t capacity;       /* particle slots per species; 0 -> 2 n_per_species + 4096  */
   double weight_m2;       /* macro-particle weight W (per area); 0 -> n0 L / n_per_species */
   double dt_s;            /* time step                                                 */
-  int32_t gather;         /* PIC_GATHER_EC (Eqs 5-7) or PIC_GATHER_MC                  */
+  int32_t gather;         /* PIC_GATHER_EC (Eqs 5-7), PIC_GATHER_MC, or PIC_GATHER_EC2
+                             (uniform grids only: S2 deposit to the nearest node and
+                             its neighbours, S1 gather of the cell-centred field; the
+                             weight beyond an electrode goes to the electrode node and
+                             the field half a cell outside it is taken as zero)      */
   int32_t precision;      /* PIC_FP64 or PIC_FP32_STATE; one value per context         */
   double gamma_see;       /* secondary electrons per absorbed ion (probability)        */
   double t_see_ev;        /* secondary-electron temperature; 0 -> 2 eV                 */
@@ -244,7 +250,8 @@ pic_status pic_set_step(pic_ctx *ctx, int32_t inst, int64_t k);
 
 /* Grid quantities of the last deposit / solve (synchronises).  Any pointer may
  * be NULL.  A_e, A_i: int64[N+1] deposit of x^k; phi: double[N+1]; E: double
- * [N] (EC cells) or [N+1] (MC nodes); E32: float, same length (FP32 form). */
+ * [N] (EC cells), [N+1] (MC nodes) or [N+2] (second-order EC: cell m-1 at
+ * entry m, zero or wrapped ghosts at 0 and N+1); E32: float, same length. */
 pic_status pic_get_fields(pic_ctx *ctx, int32_t inst, int64_t *A_e, int64_t *A_i, double *phi,
                           double *E, float *E32);
 

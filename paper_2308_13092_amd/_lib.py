@@ -326,7 +326,7 @@ class Context:
     def fields(self, inst=0):
         cfg = self.cfgs[inst]
         N = int(cfg["n_cells"]) if cfg.get("nodes") is None else len(cfg["nodes"]) - 1
-        ne = N if int(cfg.get("gather", 0)) == 0 else N + 1
+        ne = N + int(cfg.get("gather", 0))     # EC cells, MC nodes, or EC2 centres + 2 ghosts
         out = dict(A_e=np.zeros(N + 1, np.int64), A_i=np.zeros(N + 1, np.int64),
                    phi=np.zeros(N + 1), E=np.zeros(ne), E32=np.zeros(ne, np.float32))
         st = self.lib.pic_get_fields(self.ctx, inst, _ptr(out["A_e"]), _ptr(out["A_i"]),

@@ -115,8 +115,8 @@ GridLayout layout(const pic_config &c) {
   for (int p = 0; p < 2; ++p)
     for (int s = 0; s < 2; ++s) g.A[p][s] = take(8 * n1);
   g.phi = take(8 * n1);
-  g.E64 = take(8 * n1);
-  g.E32 = take(4 * n1);
+  g.E64 = take(8 * (n1 + 1));   // N cells, N + 1 nodes or N + 2 centres
+  g.E32 = take(4 * (n1 + 1));
   g.accA[0] = take(8 * n1);
   g.accA[1] = take(8 * n1);
   g.acc_phi = take(8 * n1);
@@ -150,7 +150,9 @@ std::string validate(const pic_config &c) {
     return buf;
   }
   if (c.bc != PIC_BC_DIRICHLET_RF && c.bc != PIC_BC_PERIODIC) return "bc must be 0 or 1";
-  if (c.gather != PIC_GATHER_EC && c.gather != PIC_GATHER_MC) return "gather must be 0 or 1";
+  if (c.gather != PIC_GATHER_EC && c.gather != PIC_GATHER_MC && c.gather != PIC_GATHER_EC2)
+    return "gather must be 0, 1 or 2";
+  if (c.gather == PIC_GATHER_EC2 && c.nodes) return "second-order EC needs a uniform grid";
   if (c.precision != PIC_FP64 && c.precision != PIC_FP32_STATE) return "precision must be 0 or 1";
   if (c.n_species != 1 && c.n_species != 2) return "n_species must be 1 or 2";
   if (c.nodes) {
@@ -1024,7 +1026,7 @@ pic_status pic_get_fields(pic_ctx *c, int32_t inst, int64_t *A_e, int64_t *A_i, 
   const InstDev &I = c->host_inst[inst];
   const int par = (int)(S.k & 1);
   const size_t n1 = (size_t)I.N + 1;
-  const size_t ne = I.gather == PIC_GATHER_EC ? (size_t)I.N : n1;
+  const size_t ne = I.gather == PIC_GATHER_EC ? (size_t)I.N : (I.gather == PIC_GATHER_MC ? n1 : n1 + 1);
   if (A_e) HIP_TRY(c, hipMemcpy(A_e, I.A[par][0], 8 * n1, hipMemcpyDeviceToHost));
   if (A_i && I.nsp > 1) HIP_TRY(c, hipMemcpy(A_i, I.A[par][1], 8 * n1, hipMemcpyDeviceToHost));
   if (phi) HIP_TRY(c, hipMemcpy(phi, I.phi, 8 * n1, hipMemcpyDeviceToHost));

@@ -178,6 +178,20 @@ k_field(const InstDev *__restrict__ insts, InstState *__restrict__ states, int m
       I.E64[j] = sE[j];
       I.E32[j] = (float)sE[j];
     }
+  } else if (I.gather == 2) {
+    // Second-order EC: the cell fields at the N cell centres with a ghost
+    // centre beyond each end, entry m = cell m - 1.  The S2 deposit puts the
+    // weight beyond a Dirichlet end on the electrode node, which is the
+    // energy of a ghost node at the electrode's potential: zero ghost field.
+    // A periodic box wraps.
+    for (int m = t; m <= N + 1; m += kFB) {
+      double g;
+      if (m >= 1 && m <= N) g = sE[m - 1];
+      else if (periodic) g = (m == 0) ? sE[N - 1] : sE[0];
+      else g = 0.0;
+      I.E64[m] = g;
+      I.E32[m] = (float)g;
+    }
   } else {
     for (int n = t; n <= N; n += kFB) {
       double en;

@@ -118,6 +118,44 @@ __device__ __forceinline__ void weights32(float off, int64_t &w0, int64_t &w1) {
   w0 = (int64_t)4294967296LL - (int64_t)r;
 }
 
+// Second-order EC (uniform grids): quadratic-spline (S2) deposit to the
+// nearest node n and its neighbours.  With d the signed distance to n in
+// cells (n = j, d = xi for xi < 1/2; n = j + 1, d = xi - 1 otherwise),
+// a = 1/2 - d and b = 1/2 + d formed in FP64, the fixed-point weights are
+// wl = rint(a^2 2^31) to n - 1, wr = rint(b^2 2^31) to n + 1 and
+// wc = 2^32 - wl - wr to n (the spline's (1/2-d)^2/2, 3/4-d^2, (1/2+d)^2/2).
+__device__ __forceinline__ void weights_s2(int j, double xi, int &n, int64_t &wl, int64_t &wc,
+                                           int64_t &wr) {
+  const bool up = xi >= 0.5;
+  n = up ? j + 1 : j;
+  const double a = up ? 1.5 - xi : 0.5 - xi;
+  const double b = up ? xi - 0.5 : 0.5 + xi;
+  wl = (int64_t)rint((a * a) * 2147483648.0);
+  wr = (int64_t)rint((b * b) * 2147483648.0);
+  wc = (int64_t)4294967296LL - wl - wr;
+}
+// Node of an S2 weight at m in [-1, N+1]: beyond a Dirichlet end it goes to
+// the electrode node, a periodic grid wraps it.
+__device__ __forceinline__ int fold_s2(int m, int N, int periodic) {
+  if (periodic) return m < 0 ? m + N : (m > N ? m - N : m);
+  return min(max(m, 0), N);
+}
+// Linear gather of the cell-centred field between the two centres around
+// (j, xi); the table holds N + 2 values, entry m being cell m - 1's field
+// (entries 0 and N + 1 are the ghosts outside the ends).
+__device__ __forceinline__ float gather_ec2_32(const float *E, int j, float off) {
+  const bool up = off >= 0.5f;
+  const int m = up ? j + 1 : j;
+  const float t = up ? off - 0.5f : off + 0.5f;
+  return ((1.0f - t) * E[m]) + (t * E[m + 1]);
+}
+__device__ __forceinline__ double gather_ec2_64(const double *E, int j, double xi) {
+  const bool up = xi >= 0.5;
+  const int m = up ? j + 1 : j;
+  const double t = up ? xi - 0.5 : xi + 0.5;
+  return (1.0 - t) * E[m] + t * E[m + 1];
+}
+
 // ---------------------------------------------------------------------------
 // FP32 cell walk.  The contract is the cell-by-cell walk
 //   while sigma < 0:  j -= 1 (wrap), sigma = 1 + sigma * (h_{j+1}/h_j)
@@ -349,9 +387,46 @@ struct DepAcc {
   }
 };
 
-__device__ __forceinline__ void global_deposit(int64_t *A, int j, int64_t w0, int64_t w1) {
-  atomicAdd(reinterpret_cast<unsigned long long *>(&A[j]), (unsigned long long)w0);
-  atomicAdd(reinterpret_cast<unsigned long long *>(&A[j + 1]), (unsigned long long)w1);
+// S2 deposit of one particle into the workgroup's LDS grid (the periodic
+// fold of nodes 0 and N happens when the grid is flushed).
+__device__ __forceinline__ void lds_deposit_s2(int64_t *sA, const GridPar &G, int j, double xi) {
+  int n;
+  int64_t wl, wc, wr;
+  weights_s2(j, xi, n, wl, wc, wr);
+  atomicAdd(reinterpret_cast<unsigned long long *>(&sA[fold_s2(n - 1, G.N, G.periodic)]),
+            (unsigned long long)wl);
+  atomicAdd(reinterpret_cast<unsigned long long *>(&sA[n]), (unsigned long long)wc);
+  atomicAdd(reinterpret_cast<unsigned long long *>(&sA[fold_s2(n + 1, G.N, G.periodic)]),
+            (unsigned long long)wr);
+}
+
+// One weight straight into a deposit in HBM.  Periodic nodes 0 and N are one
+// node whose total both entries hold (as a flushed LDS grid leaves them).
+__device__ __forceinline__ void global_node_add(int64_t *A, const GridPar &G, int n, int64_t w) {
+  if (G.periodic && (n == 0 || n == G.N)) {
+    atomicAdd(reinterpret_cast<unsigned long long *>(&A[0]), (unsigned long long)w);
+    atomicAdd(reinterpret_cast<unsigned long long *>(&A[G.N]), (unsigned long long)w);
+  } else {
+    atomicAdd(reinterpret_cast<unsigned long long *>(&A[n]), (unsigned long long)w);
+  }
+}
+// A particle created in a pass (ionisation product, secondary electron) goes
+// straight into the deposit of the next step with the instance's shape.
+__device__ __forceinline__ void global_deposit(CInst &I, int64_t *A, int j, double xi) {
+  const GridPar G = grid_par(I);
+  if (I.gather == 2) {
+    int n;
+    int64_t wl, wc, wr;
+    weights_s2(j, xi, n, wl, wc, wr);
+    global_node_add(A, G, fold_s2(n - 1, G.N, G.periodic), wl);
+    global_node_add(A, G, n, wc);
+    global_node_add(A, G, fold_s2(n + 1, G.N, G.periodic), wr);
+  } else {
+    int64_t w0, w1;
+    weights(xi, w0, w1);
+    global_node_add(A, G, j, w0);
+    global_node_add(A, G, j + 1, w1);
+  }
 }
 
 __device__ __forceinline__ void set_status(InstState &S, int bits) {
@@ -457,11 +532,7 @@ __device__ void emit_secondary(CInst &I, InstState &S, Smem &sm, uint64_t ion_id
   if (idx < 0) return;
   write_new<F>(I, F::view(I, 0, buf), idx, x, cell, off, vx, I.vt_see * zy, I.vt_see * zz, cid, kn);
   atomicAdd(&sm.ctr[C_SEE], 1ull);
-  if (dep) {
-    int64_t w0, w1;
-    weights(xi, w0, w1);
-    global_deposit(A_next_e, j, w0, w1);
-  }
+  if (dep) global_deposit(I, A_next_e, j, xi);
 }
 
 // ---------------------------------------------------------------------------
@@ -538,15 +609,16 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
   const unsigned long long lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int np1 = max_n + 1;
   int64_t *sA = reinterpret_cast<int64_t *>(dsm);
-  // FP32: the walk entry of every cell int4[max_n] (see walk_step), then E
-  // f32[np1].
+  // FP32: the walk entry of every cell int4[max_n] (see walk_step), then the
+  // gather table f32[np1 + 1] (N cells, N + 1 nodes, or N + 2 centres).
   const size_t a_bytes = ((size_t)np1 * 8 + 15) & ~(size_t)15;
   int4 *sT = reinterpret_cast<int4 *>(dsm + a_bytes);
   float *sE32 = reinterpret_cast<float *>(sT + max_n);
-  // FP64: E f64[np1], nodes f64[np1].
+  // FP64: the gather table f64[np1 + 1], nodes f64[np1].
   double *sE64 = reinterpret_cast<double *>(sA + np1);
-  double *sNodes = sE64 + np1;
-  const size_t tables = (F::prec == 1) ? a_bytes + (size_t)max_n * 16 + (size_t)np1 * 4 : (size_t)np1 * 24;
+  double *sNodes = sE64 + np1 + 1;
+  const size_t tables = (F::prec == 1) ? a_bytes + (size_t)max_n * 16 + (size_t)(np1 + 1) * 4
+                                       : (size_t)np1 * 24 + 8;
   int *wq = reinterpret_cast<int *>(dsm + ((tables + 15) & ~(size_t)15)) + (t >> 6) * kWaveQ;
   int wq_n = 0;   // entries in this wavefront's queue (wavefront-uniform)
 
@@ -649,7 +721,7 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
       deposit_on = (MODE == M_DEPOSIT) || (MODE == M_FUSED);
       A_out = (MODE == M_DEPOSIT) ? I.A[par][sp] : I.A[par ^ 1][sp];
       if (MODE != M_MCC) {
-        const int ne = (I.gather == 0) ? N : N + 1;
+        const int ne = (I.gather == 0) ? N : ((I.gather == 1) ? N + 1 : N + 2);
         if constexpr (F::prec == 1) {
           if (MODE != M_DEPOSIT) {
             for (int j = t; j < ne; j += BLOCK) sE32[j] = I.E32[j];
@@ -736,8 +808,9 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
           st[q] = W_IN;
           if (c[q] < 0) continue;
           const int j = c[q];
-          const float e = (gather == 0) ? sE32[j]
-                                        : ((1.0f - o[q]) * sE32[j]) + (o[q] * sE32[j + 1]);
+          const float e = (gather == 0)   ? sE32[j]
+                          : (gather == 1) ? ((1.0f - o[q]) * sE32[j]) + (o[q] * sE32[j + 1])
+                                          : gather_ec2_32(sE32, j, o[q]);
           const float v1 = vx[q] + qmdt32 * e;
           const int4 T = sT[j];
           const float sig = o[q] + v1 * __int_as_float(T.x);
@@ -794,9 +867,13 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
                 eedf_sample(I, x, (double)v1, (double)P.cold[ii].vy, (double)P.cold[ii].vz);
             }
             if constexpr (MODE == M_FUSED) {
-              int64_t w0, w1;
-              weights32(sig, w0, w1);
-              dep.add(sA, jj, w0, w1);
+              if (gather == 2) {
+                lds_deposit_s2(sA, G, jj, (double)sig);
+              } else {
+                int64_t w0, w1;
+                weights32(sig, w0, w1);
+                dep.add(sA, jj, w0, w1);
+              }
             }
           }
         }
@@ -811,12 +888,17 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
         if (c[q] < 0) continue;   // dead slot
         const int ii = (int)(i0 + q);
         if constexpr (MODE == M_DEPOSIT) {
-          int64_t w0, w1;
-          weights32(o[q], w0, w1);
-          dep.add(sA, c[q], w0, w1);
+          if (gather == 2) {
+            lds_deposit_s2(sA, G, c[q], (double)o[q]);
+          } else {
+            int64_t w0, w1;
+            weights32(o[q], w0, w1);
+            dep.add(sA, c[q], w0, w1);
+          }
         } else if constexpr (MODE == M_PULLBACK) {
-          const float e = (gather == 0) ? sE32[c[q]]
-                                        : ((1.0f - o[q]) * sE32[c[q]]) + (o[q] * sE32[c[q] + 1]);
+          const float e = (gather == 0)   ? sE32[c[q]]
+                          : (gather == 1) ? ((1.0f - o[q]) * sE32[c[q]]) + (o[q] * sE32[c[q] + 1])
+                                          : gather_ec2_32(sE32, c[q], o[q]);
           vn[q] = vx[q] - hq32 * e;
         } else if constexpr (MODE == M_MCC) {
           want[q] = coll && kn[q] <= k;
@@ -891,13 +973,19 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
         if constexpr (MODE == M_DEPOSIT) {
           double xi;
           const int j = locate64(G, sNodes, x[q], xi);
-          int64_t w0, w1;
-          weights(xi, w0, w1);
-          dep.add(sA, j, w0, w1);
+          if (gather == 2) {
+            lds_deposit_s2(sA, G, j, xi);
+          } else {
+            int64_t w0, w1;
+            weights(xi, w0, w1);
+            dep.add(sA, j, w0, w1);
+          }
         } else if constexpr (MODE == M_PULLBACK) {
           double xi;
           const int j = locate64(G, sNodes, x[q], xi);
-          const double e = (gather == 0) ? sE64[j] : (1.0 - xi) * sE64[j] + xi * sE64[j + 1];
+          const double e = (gather == 0)   ? sE64[j]
+                           : (gather == 1) ? (1.0 - xi) * sE64[j] + xi * sE64[j + 1]
+                                           : gather_ec2_64(sE64, j, xi);
           vn[q] = vx[q] - hq * e;
         } else if constexpr (MODE == M_MCC) {
           want[q] = coll && kn[q] <= k;
@@ -906,7 +994,9 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
           live_here += 1;
           double xi;
           const int j = locate64(G, sNodes, x[q], xi);
-          const double e = (gather == 0) ? sE64[j] : (1.0 - xi) * sE64[j] + xi * sE64[j + 1];
+          const double e = (gather == 0)   ? sE64[j]
+                           : (gather == 1) ? (1.0 - xi) * sE64[j] + xi * sE64[j + 1]
+                                           : gather_ec2_64(sE64, j, xi);
           const double v1 = vx[q] + qmdt * e;
           double x1 = x[q] + v1 * dt;
           vn[q] = v1;
@@ -935,9 +1025,13 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
             if constexpr (MODE == M_FUSED) {
               double xi1;
               const int j1 = locate64(G, sNodes, x1, xi1);
-              int64_t w0, w1;
-              weights(xi1, w0, w1);
-              dep.add(sA, j1, w0, w1);
+              if (gather == 2) {
+                lds_deposit_s2(sA, G, j1, xi1);
+              } else {
+                int64_t w0, w1;
+                weights(xi1, w0, w1);
+                dep.add(sA, j1, w0, w1);
+              }
             }
           }
         }
@@ -1074,11 +1168,9 @@ __device__ void drain_one(CInst &I, InstState &S, Smem &sm, int sp, int buf, int
         } else {
           j = locate64(grid_par(I), I.nodes, xx, xi);
         }
-        int64_t w0, w1;
-        weights(xi, w0, w1);
         const int par1 = (int)((k + 1) & 1);
-        if (ie >= 0) global_deposit(I.A[par1][0], j, w0, w1);
-        if (ii >= 0) global_deposit(I.A[par1][1], j, w0, w1);
+        if (ie >= 0) global_deposit(I, I.A[par1][0], j, xi);
+        if (ii >= 0) global_deposit(I, I.A[par1][1], j, xi);
       }
     }
   } else {
@@ -1273,8 +1365,8 @@ k_moments(const InstDev *__restrict__ insts, const InstState *__restrict__ state
   double *m1 = reinterpret_cast<double *>(dsm);
   double *m2 = m1 + np1;
   double *pw = m2 + np1;
-  double *sE = pw + max_n;
-  double *sNodes = sE + np1;   // FP64 form only
+  double *sE = pw + max_n;     // the gather table, up to np1 + 1 entries
+  double *sNodes = sE + np1 + 1;   // FP64 form only
   const int t = threadIdx.x, lane = __lane_id();
   const int nseg = 2 * n_inst;
   for (int j = t; j < np1; j += BLOCK) { m1[j] = 0.0; m2[j] = 0.0; }
@@ -1329,7 +1421,7 @@ k_moments(const InstDev *__restrict__ insts, const InstState *__restrict__ state
       G = grid_par(I);
       ext = S.extent[seg & 1];
       P = F::view(I, seg & 1, S.parity);
-      const int ne = (gather == 0) ? N : N + 1;
+      const int ne = (gather == 0) ? N : ((gather == 1) ? N + 1 : N + 2);
       for (int j = t; j < ne; j += BLOCK) sE[j] = I.E64[j];
       if (F::prec == 0 && !I.uniform)
         for (int j = t; j <= N; j += BLOCK) sNodes[j] = I.nodes[j];
@@ -1358,6 +1450,25 @@ k_moments(const InstDev *__restrict__ insts, const InstState *__restrict__ state
             vx = P.vx[i];
           }
         }
+      }
+      if (ok && gather == 2) {
+        // quadratic-spline weights in FP64 (the deposit's shape), per lane
+        const bool up = xi >= 0.5;
+        const int n = up ? j + 1 : j;
+        const double a = up ? 1.5 - xi : 0.5 - xi;
+        const double b = up ? xi - 0.5 : 0.5 + xi;
+        const double wl = 0.5 * (a * a), wr = 0.5 * (b * b);
+        const double wc = (1.0 - wl) - wr;
+        const int nl = fold_s2(n - 1, N, G.periodic), nr = fold_s2(n + 1, N, G.periodic);
+        const double v2 = vx * vx;
+        atomicAdd(&m1[nl], wl * vx);
+        atomicAdd(&m1[n], wc * vx);
+        atomicAdd(&m1[nr], wr * vx);
+        atomicAdd(&m2[nl], wl * v2);
+        atomicAdd(&m2[n], wc * v2);
+        atomicAdd(&m2[nr], wr * v2);
+        atomicAdd(&pw[j], vx * gather_ec2_64(sE, j, xi));
+        ok = false;
       }
       double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0, pp = 0.0;
       if (ok) {
@@ -1417,7 +1528,8 @@ __global__ void k_zero_deposit(const InstDev *__restrict__ insts, const InstStat
 size_t particle_lds_bytes(int prec, int max_n, int block) {
   const size_t np1 = (size_t)max_n + 1;
   const size_t tables =
-      (prec == 1) ? ((np1 * 8 + 15) & ~(size_t)15) + (size_t)max_n * 16 + np1 * 4 : np1 * 24;
+      (prec == 1) ? ((np1 * 8 + 15) & ~(size_t)15) + (size_t)max_n * 16 + (np1 + 1) * 4
+                  : np1 * 24 + 8;
   const size_t q = (size_t)(block / 64) * kWaveQ * sizeof(int);
   return ((tables + 15) & ~(size_t)15) + q;
 }
@@ -1506,7 +1618,7 @@ void launch_diag(const InstDev *insts, InstState *states, int inst, int prec,
 void launch_moments(const InstDev *insts, InstState *states, int n_inst, int prec, int grid, int max_n,
                     hipStream_t s) {
   const size_t np1 = (size_t)max_n + 1;
-  const size_t lds = 8 * (np1 * 3 + (size_t)max_n + (prec == 0 ? np1 : 0));
+  const size_t lds = 8 * (np1 * 3 + 1 + (size_t)max_n + (prec == 0 ? np1 : 0));
   if (prec == 1)
     hipLaunchKernelGGL(k_moments<F32>, dim3(grid), dim3(256), lds, s, insts, states, n_inst, max_n);
   else

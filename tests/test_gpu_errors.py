@@ -194,7 +194,7 @@ def test_argument_errors_leave_the_context_usable(gpu, prec):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("gather", [0, 1])
+@pytest.mark.parametrize("gather", [0, 1, 2])
 def test_cold_plasma_frequency_on_the_gpu(gpu, prec, gather):
     """Periodic box, cold electrons at cell centres displaced by
     0.01 dx sin(2 pi x/L), neutralising background: the charge perturbation
