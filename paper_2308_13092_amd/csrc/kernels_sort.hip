@@ -214,8 +214,8 @@ k_sort_scan(const InstDev *__restrict__ insts, InstState *__restrict__ states) {
 }
 
 // One particle's fields in registers.
-struct Rec32 {
-  int cell; float off, vx, vy, vz; int knext; uint64_t id;
+struct Rec32 {   // 4-byte fields only (the id as two words): kept in registers
+  int cell; float off, vx, vy, vz; int knext; uint32_t id_lo, id_hi;
 };
 struct Rec64 {
   double x, vx, vy, vz; int knext; uint64_t id;
@@ -231,15 +231,14 @@ __device__ __forceinline__ void load_recs(const P32 &P, int64_t i0, int64_t ext,
     const int4 c = gload4(P.cell + i0);
     const float4 o = gload4(P.off + i0), x = gload4(P.vx + i0);
     const int4 k = gload4(P.knext + i0);
-    Cold32 cd[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) cd[q] = gload_cold(P.cold + i0 + q);
     const int cc[4] = {c.x, c.y, c.z, c.w};
     const float oo[4] = {o.x, o.y, o.z, o.w}, xx[4] = {x.x, x.y, x.z, x.w};
     const int kk[4] = {k.x, k.y, k.z, k.w};
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      r[q] = Rec32{cc[q], oo[q], xx[q], cd[q].vy, cd[q].vz, kk[q], cd[q].id};
+      const ecpic_iv4 cd = *(const ECPIC_GLOBAL ecpic_iv4 *)(P.cold + i0 + q);
+      r[q] = Rec32{cc[q], oo[q], xx[q], __int_as_float(cd.x), __int_as_float(cd.y), kk[q],
+                   (uint32_t)cd.z, (uint32_t)cd.w};
       ok[q] = true;
     }
   } else {
@@ -247,9 +246,11 @@ __device__ __forceinline__ void load_recs(const P32 &P, int64_t i0, int64_t ext,
     for (int q = 0; q < 4; ++q) {
       const int64_t i = i0 + q;
       ok[q] = i < ext;
+      r[q] = Rec32{-1, 0.0f, 0.0f, 0.0f, 0.0f, 0, 0u, 0u};
       if (ok[q]) {
-        const Cold32 cd = gload_cold(P.cold + i);
-        r[q] = Rec32{P.cell[i], P.off[i], P.vx[i], cd.vy, cd.vz, P.knext[i], cd.id};
+        const ecpic_iv4 cd = *(const ECPIC_GLOBAL ecpic_iv4 *)(P.cold + i);
+        r[q] = Rec32{P.cell[i], P.off[i], P.vx[i], __int_as_float(cd.x), __int_as_float(cd.y),
+                     P.knext[i], (uint32_t)cd.z, (uint32_t)cd.w};
       }
     }
   }
@@ -290,7 +291,8 @@ __device__ __forceinline__ void store_rec(const P32 &P, int64_t d, const Rec32 &
   gstore<float>(P.off + d, r.off);
   gstore<float>(P.vx + d, r.vx);
   gstore<int>(P.knext + d, r.knext);
-  gstore_cold(P.cold + d, Cold32{r.vy, r.vz, r.id});
+  const ecpic_iv4 cd = {__float_as_int(r.vy), __float_as_int(r.vz), (int)r.id_lo, (int)r.id_hi};
+  *(ECPIC_GLOBAL ecpic_iv4 *)(P.cold + d) = cd;
 }
 __device__ __forceinline__ void store_rec(const P64 &P, int64_t d, const Rec64 &r) {
   gstore<double>(P.x + d, r.x);
