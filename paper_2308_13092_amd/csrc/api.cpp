@@ -997,7 +997,7 @@ pic_status pic_set_state(pic_ctx *c, int32_t inst, int32_t species, const pic_st
   }
   S.extent[species] = n;
   S.n_live[species] = n;
-  S.append[species] = 0;
+  S.append &= ~(0xFFFFFFFFull << (32 * species));
   HIP_TRY(c, hipMemcpy(c->d_state + inst, &S, sizeof S, hipMemcpyHostToDevice));
   c->deposit_current = false;
   return PIC_OK;

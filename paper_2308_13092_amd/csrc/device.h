@@ -109,7 +109,11 @@ struct InstState {
   int32_t status, parity;
   int32_t frozen, pad0;
   int64_t extent[2];
-  unsigned long long append[2];
+  // Particles appended in this pass: electrons in bits 0-31, ions in bits
+  // 32-63 (fewer than 2^31 each, capacity being at most 2^30), so one atomic
+  // reserves the two products of an ionisation.
+  unsigned long long append;
+  unsigned long long append_pad;
   unsigned long long step_live[2][kRep];
   unsigned long long step_absorbed[2][kRep];
   int64_t n_live[2];

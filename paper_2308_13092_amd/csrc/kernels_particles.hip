@@ -453,15 +453,39 @@ __device__ __forceinline__ int64_t append_slot(CInst &I, InstState &S, int s) {
   const int lane = __lane_id();
   const int leader = __ffsll((long long)active) - 1;
   const int rank = __popcll(active & ((1ull << lane) - 1ull));
-  unsigned long long base = 0;
-  if (lane == leader) base = atomicAdd(&S.append[s], (unsigned long long)__popcll(active));
-  base = __shfl(base, leader, 64);
+  unsigned long long old = 0;
+  if (lane == leader)
+    old = atomicAdd(&S.append, (unsigned long long)__popcll(active) << (32 * s));
+  old = __shfl(old, leader, 64);
+  const unsigned long long base = (old >> (32 * s)) & 0xFFFFFFFFull;
   const int64_t idx = S.extent[s] + (int64_t)(base + (unsigned long long)rank);
   if (idx >= I.cap[s]) {
     set_status(S, ST_CAPACITY);
     return -1;
   }
   return idx;
+}
+// One slot of each species (the electron and the ion of an ionisation) with
+// one atomic; -1 where that species is full.
+__device__ __forceinline__ void append_pair(CInst &I, InstState &S, int64_t &ie, int64_t &ii) {
+  const unsigned long long active = __ballot(true);
+  const int lane = __lane_id();
+  const int leader = __ffsll((long long)active) - 1;
+  const int rank = __popcll(active & ((1ull << lane) - 1ull));
+  const unsigned long long n = (unsigned long long)__popcll(active);
+  unsigned long long old = 0;
+  if (lane == leader) old = atomicAdd(&S.append, n | (n << 32));
+  old = __shfl(old, leader, 64);
+  ie = S.extent[0] + (int64_t)((old & 0xFFFFFFFFull) + (unsigned long long)rank);
+  ii = S.extent[1] + (int64_t)((old >> 32) + (unsigned long long)rank);
+  if (ie >= I.cap[0]) {
+    set_status(S, ST_CAPACITY);
+    ie = -1;
+  }
+  if (ii >= I.cap[1]) {
+    set_status(S, ST_CAPACITY);
+    ii = -1;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1142,8 +1166,8 @@ __device__ void drain_one(CInst &I, InstState &S, Smem &sm, int sp, int buf, int
       const uint64_t iid = (uint64_t)ch.z | ((uint64_t)ch.w << 32);
       double gx, gy, gz;
       gas_velocity(I, id, k, 0, gx, gy, gz);
-      const int64_t ie = append_slot(I, S, 0);
-      const int64_t ii = append_slot(I, S, 1);
+      int64_t ie, ii;
+      append_pair(I, S, ie, ii);
       int cc = 0;
       float oo = 0.0f;
       double xx = 0.0;
@@ -1245,7 +1269,7 @@ k_finalize(const InstDev *__restrict__ insts, InstState *__restrict__ states, in
           S.step_live[s][r] = 0;
           S.step_absorbed[s][r] = 0;
         }
-        int64_t add = (int64_t)S.append[s];
+        int64_t add = (int64_t)((S.append >> (32 * s)) & 0xFFFFFFFFull);
         if (S.extent[s] + add > I.cap[s]) add = I.cap[s] - S.extent[s];
         S.extent[s] += add;
         const int64_t live = (MODE == M_FUSED) ? ((int64_t)lv - (int64_t)ab + add)
@@ -1253,9 +1277,9 @@ k_finalize(const InstDev *__restrict__ insts, InstState *__restrict__ states, in
         S.n_live[s] = live;
         if ((double)live > I.growth_limit * (double)I.n_init[s] && I.n_init[s] > 0)
           S.status |= ST_GROWTH;
-        S.append[s] = 0;
       }
     }
+    if (MODE == M_MCC || MODE == M_FUSED) S.append = 0;
     if (MODE == M_MCC || MODE == M_FUSED) {
       S.k += 1;
       if (S.status != 0) S.frozen = 1;
