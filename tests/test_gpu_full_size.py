@@ -1,0 +1,107 @@
+"""Parity at full size, in the launch configuration the benchmark times.
+
+The large refined-grid discharge (0.3 m gap, 2048 cells of ratio 8, 32 M
+electrons + 32 M ions, 1024-thread workgroups, graph-replayed fused steps, a
+sort every 20 steps) runs on the GPU, in the FP32 state form the benchmark
+reports and in the FP64 form it times beside it.  The oracle cannot advance 64 M
+particles in seconds, so the checks split:
+
+* the whole deposit of x^k, node by node, against the oracle's deposit of the
+  GPU's state (an exact int64 sum: bitwise);
+* phi^k and E^k from that deposit, normwise;
+* one fused step for a random sample of particles of each species, which the
+  oracle advances one by one in the field of the whole deposit (push,
+  absorption, secondary emission, collisions and their products, matched by
+  id).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from gpu_common import compare_species, normwise, qmdt_abs
+from oracle import physics as ph
+from oracle.pic import FP32, FP64, Species
+from oracle.sim import Sim
+
+pytestmark = pytest.mark.gpu
+
+K_STEPS = 25          # past the sort of step 20
+SAMPLE = 50_000       # particles per species advanced by the oracle
+
+
+def note(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def species(st, s, idx=None):
+    take = (lambda a: a) if idx is None else (lambda a: a[idx])
+    pos = dict(x=take(st["x"]).copy()) if "x" in st else dict(cell=take(st["cell"]).copy(),
+                                                                off=take(st["off"]).copy())
+    return Species(s=s, prec=FP64 if "x" in st else FP32, vx=take(st["vx"]).copy(),
+                   vy=take(st["vy"]).copy(), vz=take(st["vz"]).copy(), id=take(st["id"]).copy(),
+                   knext=take(st["knext"]).astype(np.int64), **pos)
+
+
+def as_dict(sp):
+    pos = dict(x=sp.x) if sp.prec == FP64 else dict(cell=sp.cell, off=sp.off)
+    return dict(vx=sp.vx, vy=sp.vy, vz=sp.vz, id=sp.id, knext=sp.knext, **pos)
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_large_workload_against_the_oracle(gpu, prec):
+    from paper_2308_13092_amd import Context, configs
+    base = configs.large(precision=prec)
+    n_g = ph.gas_density(base["p_pa"], base["t_gas_k"])
+    # the null-collision bounds the oracle uses, handed to both sides as the same doubles
+    cfg = dict(base, nu_max_e=ph.nu_max_electron(n_g),
+               nu_max_i=ph.nu_max_ion(n_g, base["v_rf"], base["t_gas_k"]))
+    note("large workload", prec, cfg["n_per_species"], cfg["n_cells"])
+    ctx = Context([cfg])
+    assert ctx.tuning()["block"] == 1024 and ctx.tuning()["use_graph"] == 1
+    ctx.step(K_STEPS)
+    d = ctx.diagnostics()
+    k = int(d["step"])
+    states = [ctx.get_state(0, s) for s in range(2)]
+    f = ctx.fields()
+    note("state at step", k, [len(st["id"]) for st in states])
+
+    # Deposit of x^k over every particle, and the exact total charge.
+    full = Sim(cfg, species=[species(st, s) for s, st in enumerate(states)], k=k)
+    A = full.deposit()
+    assert np.array_equal(f["A_e"], A[0])
+    assert np.array_equal(f["A_i"], A[1])
+    for s in range(2):
+        assert int(A[s].sum()) == len(states[s]["id"]) * 2 ** 32
+
+    # phi^k and E^k solved from that deposit.
+    ctx.poisson()
+    f = ctx.fields()
+    full.solve()
+    assert normwise(f["phi"], full.phi) <= 1e-12
+    tol_e = 1e-12 + 64 * np.finfo(float).eps * np.max(np.abs(full.phi)) / (
+        np.min(full.grid.h) * np.max(np.abs(full.E)))
+    assert normwise(f["E"], full.E) <= tol_e
+    emax = float(np.max(np.abs(full.E)))
+
+    # One fused step: the sample in the oracle, in the field of all particles.
+    rng = np.random.Generator(np.random.PCG64(20240))
+    picks = [np.sort(rng.choice(len(st["id"]), SAMPLE, replace=False)) for st in states]
+    sample = Sim(cfg, species=[species(st, s, picks[s]) for s, st in enumerate(states)], k=k)
+    sample.deposit = lambda: setattr(sample, "A", A) or A
+    del full
+    ctx.step(1)
+    sample.step()
+    after = [ctx.get_state(0, s) for s in range(2)]
+    for s in range(2):
+        ref = as_dict(sample.sp[s])
+        g = after[s]
+        mine = np.isin(g["id"], ref["id"])
+        gpu = {key: v[mine] for key, v in g.items()}
+        vs = float(np.max(np.abs(states[s]["vx"].astype(np.float64)))) + qmdt_abs(cfg, s) * emax
+        rel = 1e-5 if prec == 1 else tol_e
+        stats = compare_species(gpu, ref, sample.grid, rel, rel, vs, max_flips=3)
+        note("species", s, "sample", len(ref["id"]), stats)
+        assert stats["common"] >= 0.99 * SAMPLE
+    ctx.close()
