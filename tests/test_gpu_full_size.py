@@ -1,4 +1,4 @@
-"""Parity at full size, in the launch configuration the benchmark times.
+"""Parity at full size, in the launch configurations the benchmark times.
 
 The large refined-grid discharge (0.3 m gap, 2048 cells of ratio 8, 32 M
 electrons + 32 M ions, 1024-thread workgroups, graph-replayed fused steps, a
@@ -105,3 +105,33 @@ def test_large_workload_against_the_oracle(gpu, prec):
         note("species", s, "sample", len(ref["id"]), stats)
         assert stats["common"] >= 0.99 * SAMPLE
     ctx.close()
+
+
+def test_batched_sweep_at_full_size(gpu):
+    """The 256-discharge sweep as the benchmark runs it (one graph-replayed
+    step for all of them): the largest discharge and two others end bitwise
+    as each does alone, and their deposits equal the oracle's deposit of the
+    batch's state."""
+    from paper_2308_13092_amd import Context, configs
+    cfgs = configs.sweep(256)
+    sizes = [c["n_per_species"] for c in cfgs]
+    picks = [int(np.argmax(sizes)), 7, 200]
+    note("sweep", len(cfgs), "picks", picks, [sizes[i] for i in picks])
+    batch = Context(cfgs)
+    batch.step(25)
+    for i in picks:
+        states = [batch.get_state(i, s) for s in range(2)]
+        f = batch.fields(i)
+        k = int(batch.diagnostics(i)["step"])
+        A = Sim(cfgs[i], species=[species(st, s) for s, st in enumerate(states)], k=k).deposit()
+        assert np.array_equal(f["A_e"], A[0]) and np.array_equal(f["A_i"], A[1]), i
+        alone = Context([cfgs[i]])
+        alone.step(25)
+        for s in range(2):
+            a, b = states[s], alone.get_state(0, s)
+            oa, ob = np.argsort(a["id"]), np.argsort(b["id"])
+            for key in a:
+                assert np.array_equal(a[key][oa], b[key][ob]), (i, s, key)
+        note("discharge", i, "step", k, [len(st["id"]) for st in states])
+        alone.close()
+    batch.close()
