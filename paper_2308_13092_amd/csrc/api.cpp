@@ -138,8 +138,7 @@ GridLayout layout(const pic_config &c) {
 }
 
 size_t static_bytes(int n) {
-  return align_up(sizeof(InstDev) * n) + align_up(sizeof(InstState) * n) + align_up(64) +
-         align_up(8 * D_NWORDS);
+  return align_up(sizeof(InstDev) * n) + align_up(sizeof(InstState) * n) + align_up(8 * D_NWORDS);
 }
 
 std::string validate(const pic_config &c) {
@@ -225,7 +224,6 @@ struct pic_ctx {
   std::vector<InstDev> host_inst;
   InstDev *d_inst = nullptr;
   InstState *d_state = nullptr;
-  unsigned int *d_done = nullptr;   // [0] particles, [1] sort
   unsigned long long *d_diag = nullptr;
   int max_n = 2;
   pic_tuning tune{1024, 0, 0, 1};   // 1024 threads per block: measured fastest on the large workload
@@ -483,11 +481,11 @@ static pic_status deposit_only(pic_ctx *c, int only) {
   }
   launch_zero_deposit(c->d_inst, c->d_state, c->n_inst, st);
   HIP_TRY(c, launch_particles(c->d_inst, c->d_state, c->n_inst, c->prec, M_DEPOSIT, 256,
-                              particle_grid(c), c->max_n, c->d_done, st));
+                              particle_grid(c), c->max_n, st));
   if (only >= 0 && c->slots[only].cfg.pullback) {
     launch_field(c->d_inst, c->d_state, c->n_inst, 0, st);
     HIP_TRY(c, launch_particles(c->d_inst, c->d_state, c->n_inst, c->prec, M_PULLBACK, 256,
-                                particle_grid(c), c->max_n, c->d_done, st));
+                                particle_grid(c), c->max_n, st));
   }
   if (only >= 0) {
     for (int i = 0; i < c->n_inst; ++i)
@@ -570,15 +568,13 @@ static pic_status enqueue_step(pic_ctx *c, hipStream_t st, bool sort, bool timed
   }
   if (timed) { pic_status r = ev_end(c); if (r) return r; r = ev_begin(c, 1); if (r) return r; }
   HIP_TRY(c, launch_particles(c->d_inst, c->d_state, c->n_inst, c->prec, M_FUSED, c->tune.block,
-                              particle_grid(c), c->max_n, c->d_done, st));
+                              particle_grid(c), c->max_n, st));
   if (timed) { pic_status r = ev_end(c); if (r) return r; r = ev_begin(c, 3); if (r) return r; }
-  HIP_TRY(c, launch_drain(c->d_inst, c->d_state, c->n_inst, c->prec, M_FUSED, drain_grid(c),
-                          c->d_done, st));
+  HIP_TRY(c, launch_drain(c->d_inst, c->d_state, c->n_inst, c->prec, M_FUSED, drain_grid(c), st));
   if (timed) { pic_status r = ev_end(c); if (r) return r; }
   if (sort) {
     if (timed) { pic_status r = ev_begin(c, 2); if (r) return r; }
-    HIP_TRY(c, launch_sort(c->d_inst, c->d_state, c->n_inst, c->prec, sort_grid(c), c->max_n,
-                           c->d_done + 1, st));
+    HIP_TRY(c, launch_sort(c->d_inst, c->d_state, c->n_inst, c->prec, sort_grid(c), c->max_n, st));
     if (timed) { pic_status r = ev_end(c); if (r) return r; }
   }
   return PIC_OK;
@@ -685,8 +681,6 @@ pic_status pic_init(const pic_config *cfgs, int32_t n_inst, void *device_arena, 
   o += align_up(sizeof(InstDev) * n_inst);
   c->d_state = (InstState *)(c->arena + o);
   o += align_up(sizeof(InstState) * n_inst);
-  c->d_done = (unsigned int *)(c->arena + o);
-  o += align_up(64);
   c->d_diag = (unsigned long long *)(c->arena + o);
   o += align_up(8 * D_NWORDS);
   c->pool.reset(align_up(o), arena_bytes);
@@ -739,7 +733,7 @@ pic_status pic_deposit(pic_ctx *c) {
   if (!c) return PIC_EINVAL;
   launch_zero_deposit(c->d_inst, c->d_state, c->n_inst, c->stream);
   HIP_TRY(c, launch_particles(c->d_inst, c->d_state, c->n_inst, c->prec, M_DEPOSIT, 256,
-                              particle_grid(c), c->max_n, c->d_done, c->stream));
+                              particle_grid(c), c->max_n, c->stream));
   c->deposit_current = true;
   return PIC_OK;
 }
@@ -759,9 +753,8 @@ pic_status pic_poisson(pic_ctx *c) {
 pic_status pic_gather_push(pic_ctx *c) {
   if (!c) return PIC_EINVAL;
   HIP_TRY(c, launch_particles(c->d_inst, c->d_state, c->n_inst, c->prec, M_PUSH, 256,
-                              particle_grid(c), c->max_n, c->d_done, c->stream));
-  HIP_TRY(c, launch_drain(c->d_inst, c->d_state, c->n_inst, c->prec, M_PUSH, drain_grid(c),
-                          c->d_done, c->stream));
+                              particle_grid(c), c->max_n, c->stream));
+  HIP_TRY(c, launch_drain(c->d_inst, c->d_state, c->n_inst, c->prec, M_PUSH, drain_grid(c), c->stream));
   c->deposit_current = false;
   return PIC_OK;
 }
@@ -769,9 +762,8 @@ pic_status pic_gather_push(pic_ctx *c) {
 pic_status pic_mcc(pic_ctx *c) {
   if (!c) return PIC_EINVAL;
   HIP_TRY(c, launch_particles(c->d_inst, c->d_state, c->n_inst, c->prec, M_MCC, 256,
-                              particle_grid(c), c->max_n, c->d_done, c->stream));
-  HIP_TRY(c, launch_drain(c->d_inst, c->d_state, c->n_inst, c->prec, M_MCC, drain_grid(c),
-                          c->d_done, c->stream));
+                              particle_grid(c), c->max_n, c->stream));
+  HIP_TRY(c, launch_drain(c->d_inst, c->d_state, c->n_inst, c->prec, M_MCC, drain_grid(c), c->stream));
   c->deposit_current = false;
   c->host_step++;
   return PIC_OK;
@@ -779,8 +771,7 @@ pic_status pic_mcc(pic_ctx *c) {
 
 pic_status pic_sort(pic_ctx *c) {
   if (!c) return PIC_EINVAL;
-  HIP_TRY(c, launch_sort(c->d_inst, c->d_state, c->n_inst, c->prec, sort_grid(c), c->max_n,
-                         c->d_done + 1, c->stream));
+  HIP_TRY(c, launch_sort(c->d_inst, c->d_state, c->n_inst, c->prec, sort_grid(c), c->max_n, c->stream));
   return PIC_OK;
 }
 

@@ -17,14 +17,13 @@ void launch_init(const InstDev *insts, InstState *states, int inst, int species,
                  double t_ev, int64_t n, hipStream_t s);
 // Persistent pass over every particle of every active instance.
 hipError_t launch_particles(const InstDev *insts, InstState *states, int n_inst, int prec,
-                            int mode, int block, int grid, int max_n, unsigned int *done,
-                            hipStream_t s);
-// Drain of the queued particles of a push / collision pass (closes the step
-// in the collision and fused modes).
+                            int mode, int block, int grid, int max_n, hipStream_t s);
+// Drain of the queued particles of a push / collision pass, then the pass's
+// closing kernel (which ends the step in the collision and fused modes).
 hipError_t launch_drain(const InstDev *insts, InstState *states, int n_inst, int prec, int mode,
-                        int grid, unsigned int *done, hipStream_t s);
+                        int grid, hipStream_t s);
 hipError_t launch_sort(const InstDev *insts, InstState *states, int n_inst, int prec, int grid,
-                       int max_n, unsigned int *done, hipStream_t s);
+                       int max_n, hipStream_t s);
 void launch_diag(const InstDev *insts, InstState *states, int inst, int prec,
                  unsigned long long *out, hipStream_t s);
 void launch_zero_deposit(const InstDev *insts, InstState *states, int n_inst, hipStream_t s);

@@ -20,11 +20,12 @@
 //
 // Gather tables (E, dt/h, neighbour ratios; for FP64 the nodes and widths)
 // are staged in LDS when a workgroup enters a segment.  The deposit goes to
-// an LDS int64 copy of the grid: each lane first merges its own run of equal
-// cells, then runs of equal cells across the wavefront are summed by their
-// first lane (sorted particles make nearly every lane of a wavefront share
-// one or two cells), and only the run leaders issue LDS atomics.  At the end
-// of a segment the nonzero LDS entries are added to HBM with one atomic each.
+// an LDS int64 copy of the grid: each lane sums its own consecutive particles
+// of one cell in registers (the usual case in a cell-sorted state) and adds
+// the sum with one LDS atomic per node; a particle in another cell goes to
+// LDS at once (the quadratic-spline deposit of second-order EC always does).
+// At the end of a segment the nonzero LDS entries are added to HBM with one
+// atomic each.
 #include "device.h"
 #include "kernels.h"
 
@@ -566,8 +567,8 @@ __device__ void emit_secondary(CInst &I, InstState &S, Smem &sm, uint64_t ion_id
 // live particle, deposits x^{k+1} into the LDS grid and writes the state back.
 // Particles that leave the gap or are collision candidates this step (a few
 // percent) are not handled in place: their indices go to a per-wavefront
-// queue in LDS (slots from a ballot) and, 64 at a time, to a per-segment queue
-// in HBM (one atomic per 64 entries).  k_drain then processes those queues
+// queue in LDS (slots from a ballot) and, kSpill at a time, to a per-segment
+// queue in HBM (one atomic per chunk).  k_drain then processes those queues
 // with full wavefronts: absorption tallies, secondary emission, the FP64
 // collision arithmetic and ionisation products.  Keeping the rare, heavy code
 // out of the streaming kernel keeps its register footprint small.
@@ -1212,13 +1213,11 @@ __device__ void drain_one(CInst &I, InstState &S, Smem &sm, int sp, int buf, int
   P.knext[i] = next_candidate(id, k, sp, I.seed, I.nudt[sp]);
 }
 
-// Drain the per-segment queues with full wavefronts; in the modes that end a
-// step the last workgroup to finish also closes the step: new particles join
-// the extents, the live count is updated and checked, and k advances.
+// Drain the per-segment queues with full wavefronts (k_finalize then closes
+// the pass).
 template <class F, int MODE>
 __global__ void __launch_bounds__(256)
-k_drain(const InstDev *__restrict__ insts, InstState *__restrict__ states, int n_inst,
-        unsigned int *__restrict__ done) {
+k_drain(const InstDev *__restrict__ insts, InstState *__restrict__ states, int n_inst) {
   constexpr int BLOCK = 256;
   __shared__ Smem sm;
   const int t = threadIdx.x;
@@ -1560,28 +1559,27 @@ size_t particle_lds_bytes(int prec, int max_n, int block) {
 
 template <class F, int MODE, int BLOCK>
 static hipError_t launch_pk(const InstDev *insts, InstState *states, int n_inst, int grid,
-                            int max_n, unsigned int *done, hipStream_t s) {
+                            int max_n, hipStream_t s) {
   const size_t lds = particle_lds_bytes(F::prec, max_n, BLOCK);
   hipLaunchKernelGGL((k_particles<F, MODE, BLOCK>), dim3(grid), dim3(BLOCK), lds, s, insts, states,
                      n_inst, max_n);
-  (void)done;
   return hipGetLastError();
 }
 
 template <class F>
 static hipError_t launch_drain_form(const InstDev *insts, InstState *states, int n_inst, int mode,
-                                    int grid, unsigned int *done, hipStream_t s) {
+                                    int grid, hipStream_t s) {
   switch (mode) {
     case M_PUSH:
-      hipLaunchKernelGGL((k_drain<F, M_PUSH>), dim3(grid), dim3(256), 0, s, insts, states, n_inst, done);
+      hipLaunchKernelGGL((k_drain<F, M_PUSH>), dim3(grid), dim3(256), 0, s, insts, states, n_inst);
       hipLaunchKernelGGL((k_finalize<M_PUSH>), dim3(1), dim3(256), 0, s, insts, states, n_inst);
       break;
     case M_MCC:
-      hipLaunchKernelGGL((k_drain<F, M_MCC>), dim3(grid), dim3(256), 0, s, insts, states, n_inst, done);
+      hipLaunchKernelGGL((k_drain<F, M_MCC>), dim3(grid), dim3(256), 0, s, insts, states, n_inst);
       hipLaunchKernelGGL((k_finalize<M_MCC>), dim3(1), dim3(256), 0, s, insts, states, n_inst);
       break;
     case M_FUSED:
-      hipLaunchKernelGGL((k_drain<F, M_FUSED>), dim3(grid), dim3(256), 0, s, insts, states, n_inst, done);
+      hipLaunchKernelGGL((k_drain<F, M_FUSED>), dim3(grid), dim3(256), 0, s, insts, states, n_inst);
       hipLaunchKernelGGL((k_finalize<M_FUSED>), dim3(1), dim3(256), 0, s, insts, states, n_inst);
       break;
     default:
@@ -1593,32 +1591,32 @@ static hipError_t launch_drain_form(const InstDev *insts, InstState *states, int
 // The number of queued particles is only known on the device, so the drain
 // grid is fixed and its workgroups split whatever the queues hold.
 hipError_t launch_drain(const InstDev *insts, InstState *states, int n_inst, int prec, int mode,
-                        int grid, unsigned int *done, hipStream_t s) {
-  if (prec == 1) return launch_drain_form<F32>(insts, states, n_inst, mode, grid, done, s);
-  return launch_drain_form<F64>(insts, states, n_inst, mode, grid, done, s);
+                        int grid, hipStream_t s) {
+  if (prec == 1) return launch_drain_form<F32>(insts, states, n_inst, mode, grid, s);
+  return launch_drain_form<F64>(insts, states, n_inst, mode, grid, s);
 }
 
 template <class F>
 static hipError_t launch_form(const InstDev *insts, InstState *states, int n_inst, int mode,
-                              int block, int grid, int max_n, unsigned int *done, hipStream_t s) {
+                              int block, int grid, int max_n, hipStream_t s) {
   if (mode == M_FUSED && block == 512)
-    return launch_pk<F, M_FUSED, 512>(insts, states, n_inst, grid, max_n, done, s);
+    return launch_pk<F, M_FUSED, 512>(insts, states, n_inst, grid, max_n, s);
   if (mode == M_FUSED && block == 1024)
-    return launch_pk<F, M_FUSED, 1024>(insts, states, n_inst, grid, max_n, done, s);
+    return launch_pk<F, M_FUSED, 1024>(insts, states, n_inst, grid, max_n, s);
   switch (mode) {
-    case M_DEPOSIT: return launch_pk<F, M_DEPOSIT, 256>(insts, states, n_inst, grid, max_n, done, s);
-    case M_PUSH: return launch_pk<F, M_PUSH, 256>(insts, states, n_inst, grid, max_n, done, s);
-    case M_MCC: return launch_pk<F, M_MCC, 256>(insts, states, n_inst, grid, max_n, done, s);
-    case M_FUSED: return launch_pk<F, M_FUSED, 256>(insts, states, n_inst, grid, max_n, done, s);
-    case M_PULLBACK: return launch_pk<F, M_PULLBACK, 256>(insts, states, n_inst, grid, max_n, done, s);
+    case M_DEPOSIT: return launch_pk<F, M_DEPOSIT, 256>(insts, states, n_inst, grid, max_n, s);
+    case M_PUSH: return launch_pk<F, M_PUSH, 256>(insts, states, n_inst, grid, max_n, s);
+    case M_MCC: return launch_pk<F, M_MCC, 256>(insts, states, n_inst, grid, max_n, s);
+    case M_FUSED: return launch_pk<F, M_FUSED, 256>(insts, states, n_inst, grid, max_n, s);
+    case M_PULLBACK: return launch_pk<F, M_PULLBACK, 256>(insts, states, n_inst, grid, max_n, s);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_particles(const InstDev *insts, InstState *states, int n_inst, int prec, int mode,
-                            int block, int grid, int max_n, unsigned int *done, hipStream_t s) {
-  if (prec == 1) return launch_form<F32>(insts, states, n_inst, mode, block, grid, max_n, done, s);
-  return launch_form<F64>(insts, states, n_inst, mode, block, grid, max_n, done, s);
+                            int block, int grid, int max_n, hipStream_t s) {
+  if (prec == 1) return launch_form<F32>(insts, states, n_inst, mode, block, grid, max_n, s);
+  return launch_form<F64>(insts, states, n_inst, mode, block, grid, max_n, s);
 }
 
 void launch_init(const InstDev *insts, InstState *states, int inst, int species, int prec,

@@ -2,9 +2,9 @@
 //
 // Every sort_interval steps the particles of each (instance, species) segment
 // are reordered by cell into the other particle buffer and absorbed particles
-// are dropped.  Sorted particles keep the deposit of a wavefront on one or two
-// nodes (cheap to merge before the LDS atomics) and keep each workgroup's
-// share of the grid small.  Three passes:
+// are dropped.  In a sorted state a lane's consecutive particles share a cell
+// (their deposit merges in registers before the LDS atomics) and each
+// workgroup's share of the grid stays small.  Three passes:
 //   count   per-workgroup LDS histogram of the live cells, added to HBM;
 //   scan    one workgroup per instance: exclusive prefix of the counts gives
 //           each cell's first destination slot;
@@ -324,7 +324,7 @@ __device__ __forceinline__ int rec_key(CInst &I, const Rec64 &r, const double *n
 template <class P>
 __global__ void __launch_bounds__(kSB)
 k_sort_scatter(const InstDev *__restrict__ insts, InstState *__restrict__ states, int n_inst,
-               int max_n, unsigned int *__restrict__ done) {
+               int max_n) {
   __shared__ SortSmem sm;
   extern __shared__ __align__(16) unsigned char dsm[];
   // LDS: per-cell counts u32, per-cell destination bases u64 and, FP64
@@ -415,7 +415,7 @@ size_t sort_lds_bytes(int max_n, int prec) {
 }
 
 hipError_t launch_sort(const InstDev *insts, InstState *states, int n_inst, int prec, int grid,
-                       int max_n, unsigned int *done, hipStream_t s) {
+                       int max_n, hipStream_t s) {
   const size_t lds = sort_lds_bytes(max_n, prec);
   // The count needs only the histogram (and, FP64, the nodes to locate x).
   const size_t lds_count = 4 * (size_t)((max_n + 2) & ~1) + (prec == 0 ? 8 * (size_t)(max_n + 1) : 0);
@@ -425,9 +425,9 @@ hipError_t launch_sort(const InstDev *insts, InstState *states, int n_inst, int 
     hipLaunchKernelGGL(k_sort_count<P64>, dim3(grid), dim3(kSB), lds_count, s, insts, states, n_inst, max_n);
   hipLaunchKernelGGL(k_sort_scan, dim3(n_inst), dim3(kSB), 0, s, insts, states);
   if (prec == 1)
-    hipLaunchKernelGGL(k_sort_scatter<P32>, dim3(grid), dim3(kSB), lds, s, insts, states, n_inst, max_n, done);
+    hipLaunchKernelGGL(k_sort_scatter<P32>, dim3(grid), dim3(kSB), lds, s, insts, states, n_inst, max_n);
   else
-    hipLaunchKernelGGL(k_sort_scatter<P64>, dim3(grid), dim3(kSB), lds, s, insts, states, n_inst, max_n, done);
+    hipLaunchKernelGGL(k_sort_scatter<P64>, dim3(grid), dim3(kSB), lds, s, insts, states, n_inst, max_n);
   hipLaunchKernelGGL(k_sort_finish, dim3(1), dim3(256), 0, s, insts, states, n_inst);
   return hipGetLastError();
 }
