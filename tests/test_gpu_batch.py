@@ -115,6 +115,27 @@ def test_graph_replay_equals_eager_launches(gpu, prec):
         assert_same_instance(a, i, b, i)
 
 
+@pytest.mark.parametrize("use_graph", [1, 0])
+def test_kernel_timing_changes_nothing(gpu, use_graph):
+    """Timed steps (eager launches with HIP events between the kernels, also
+    when graphs are on) give the untimed graph results bitwise, and count every
+    stage: 60 steps with three sorts."""
+    cfgs = [c for c in mixed_configs(1) if c["n_cells"] > 0][:3]
+    note("timing", use_graph)
+    a, b = Context()(cfgs), Context()(cfgs)
+    a.set_tuning(use_graph=use_graph, sort_interval=20)
+    b.set_tuning(use_graph=1, sort_interval=20)
+    a.kernel_times(True)
+    a.step(60)
+    kt = a.kernel_times(False)
+    b.step(60)
+    assert kt["particle_launches"] == 60 and kt["field_launches"] == 60
+    assert kt["drain_launches"] == 60 and kt["sort_launches"] == 3
+    assert kt["particle_ms"] > 0 and kt["field_ms"] > 0 and kt["drain_ms"] > 0 and kt["sort_ms"] > 0
+    for i in range(len(cfgs)):
+        assert_same_instance(a, i, b, i)
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("block,bpc", [(256, 1), (1024, 0), (512, 5)])
 def test_launch_shape_does_not_change_results(gpu, block, bpc, prec):
