@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define PIC_ABI_VERSION 3
+#define PIC_ABI_VERSION 4
 
 typedef struct pic_ctx pic_ctx;  /* opaque; owns host-side metadata only */
 
@@ -180,13 +180,14 @@ typedef struct pic_tuning {
 } pic_tuning;
 
 /* Kernel timing (pic_kernel_times).  Durations in milliseconds summed over the
- * launches recorded since timing was enabled. */
+ * launches recorded since timing was enabled: the streaming pass on every
+ * step, the sort on every sort, the field and the drain on every 16th timed
+ * step (each HIP event costs the stream a few microseconds). */
 typedef struct pic_kernel_time {
   double field_ms;      int64_t field_launches;     /* Poisson + field (one block per instance) */
   double particle_ms;   int64_t particle_launches;  /* streaming pass: gather, push, deposit    */
   double drain_ms;      int64_t drain_launches;     /* queued particles: collisions, absorption */
   double sort_ms;       int64_t sort_launches;      /* cell sort + compaction (3 kernels)        */
-  int64_t particles;    /* live particles processed by the timed particle launches */
 } pic_kernel_time;
 
 int32_t pic_abi_version(void);

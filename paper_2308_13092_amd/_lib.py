@@ -70,7 +70,7 @@ class pic_kernel_time(C.Structure):
     _fields_ = [("field_ms", C.c_double), ("field_launches", C.c_int64),
                 ("particle_ms", C.c_double), ("particle_launches", C.c_int64),
                 ("drain_ms", C.c_double), ("drain_launches", C.c_int64),
-                ("sort_ms", C.c_double), ("sort_launches", C.c_int64), ("particles", C.c_int64)]
+                ("sort_ms", C.c_double), ("sort_launches", C.c_int64)]
 
 
 # (name, restype, argtypes) of every entry point declared in include/ecpic.h.
