@@ -176,7 +176,8 @@ typedef struct pic_tuning {
   int32_t blocks_per_cu;  /* persistent particle-kernel blocks per compute unit (1-16;
                              0 = as many as the CU's LDS holds at once, at most 8)     */
   int32_t sort_interval;  /* steps between cell sorts (0 = never)                     */
-  int32_t use_graph;      /* 1 = replay pic_step through captured HIP graphs          */
+  int32_t use_graph;      /* 1 = replay pic_step through captured HIP graphs; 0 = plain
+                             launches (default: measured faster here)                */
 } pic_tuning;
 
 /* Kernel timing (pic_kernel_times).  Durations in milliseconds summed over the

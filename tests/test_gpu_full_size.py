@@ -1,8 +1,8 @@
 """Parity at full size, in the launch configurations the benchmark times.
 
 The large refined-grid discharge (0.3 m gap, 2048 cells of ratio 8, 32 M
-electrons + 32 M ions, 1024-thread workgroups, graph-replayed fused steps, a
-sort every 20 steps) runs on the GPU, in the FP32 state form the benchmark
+electrons + 32 M ions, 1024-thread workgroups, fused steps launched with the
+default tuning, a sort every 20 steps) runs on the GPU, in the FP32 state form the benchmark
 reports and in the FP64 form it times beside it.  The oracle cannot advance 64 M
 particles in seconds, so the checks split:
 
@@ -59,7 +59,7 @@ def test_large_workload_against_the_oracle(gpu, prec):
                nu_max_i=ph.nu_max_ion(n_g, base["v_rf"], base["t_gas_k"]))
     note("large workload", prec, cfg["n_per_species"], cfg["n_cells"])
     ctx = Context([cfg])
-    assert ctx.tuning()["block"] == 1024 and ctx.tuning()["use_graph"] == 1
+    assert ctx.tuning()["block"] == 1024          # the benchmark's default launch shape
     ctx.step(K_STEPS)
     d = ctx.diagnostics()
     k = int(d["step"])
@@ -108,8 +108,8 @@ def test_large_workload_against_the_oracle(gpu, prec):
 
 
 def test_batched_sweep_at_full_size(gpu):
-    """The 256-discharge sweep as the benchmark runs it (one graph-replayed
-    step for all of them): the largest discharge and two others end bitwise
+    """The 256-discharge sweep as the benchmark runs it (one step launch for
+    all of them): the largest discharge and two others end bitwise
     as each does alone, and their deposits equal the oracle's deposit of the
     batch's state."""
     from paper_2308_13092_amd import Context, configs
