@@ -270,30 +270,47 @@ static void drop_graphs(pic_ctx *c) {
   c->graph_max_n = -1;
 }
 
+// Called whenever the set of slots changes: the grid bound and the grid
+// sizes (which follow the slots' capacities) change with it, so the captured
+// graphs are dropped.
 static void recompute_max_n(pic_ctx *c) {
   int m = 2;
   for (auto &s : c->slots)
     if (s.used) m = std::max(m, (int)s.cfg.n_cells);
-  m = (m + 3) / 4 * 4;
-  if (m != c->max_n) {
-    c->max_n = m;
-    drop_graphs(c);
-  }
+  c->max_n = (m + 3) / 4 * 4;
+  drop_graphs(c);
 }
 
-// Workgroups per CU of the persistent particle kernel: the tuned value, or
-// as many as fit in the CU's 160 KB of LDS at once (so that every workgroup
-// of the persistent grid is resident together), at most 8.
-static int particle_grid(const pic_ctx *c) {
+// Tiles of `tile` particles (or queue entries) that the slots' capacities
+// can hold: workgroups of a persistent grid beyond that number would only
+// start and exit, which costs microseconds on small discharges.
+static int64_t capacity_tiles(const pic_ctx *c, int64_t tile) {
+  int64_t t = 0;
+  for (int i = 0; i < c->n_inst; ++i) {
+    if (!c->slots[i].used) continue;
+    const InstDev &I = c->host_inst[i];
+    for (int s = 0; s < I.nsp; ++s) t += (I.cap[s] + tile - 1) / tile;
+  }
+  return std::max<int64_t>(t, 1);
+}
+static int capped(const pic_ctx *c, int64_t grid, int64_t tile) {
+  return (int)std::max<int64_t>(1, std::min(grid, capacity_tiles(c, tile)));
+}
+
+// Workgroups of the persistent particle kernel (of `block` threads): per CU
+// the tuned value, or as many as fit in the CU's 160 KB of LDS at once (so
+// that every workgroup of the persistent grid is resident together), at most
+// 8; never more than the tiles the capacities hold.
+static int particle_grid(const pic_ctx *c, int block) {
   int per = c->tune.blocks_per_cu;
   if (per <= 0) {
     const size_t lds = particle_lds_bytes(c->prec, c->max_n, c->tune.block) + 8192;
     per = (int)std::min<size_t>(8, std::max<size_t>(1, (160 * 1024) / lds));
   }
-  return c->n_cu * per;
+  return capped(c, (int64_t)c->n_cu * per, (int64_t)block * kParticlesPerThread);
 }
-static int sort_grid(const pic_ctx *c) { return c->n_cu * 4; }
-static int drain_grid(const pic_ctx *c) { return c->n_cu * 4; }
+static int sort_grid(const pic_ctx *c) { return capped(c, (int64_t)c->n_cu * 4, kSortTile); }
+static int drain_grid(const pic_ctx *c) { return capped(c, (int64_t)c->n_cu * 4, kDrainTile); }
 
 // Fill InstDev for slot i from its config and block offset; write host arrays.
 static pic_status setup_slot(pic_ctx *c, int i, const pic_config &cfg) {
@@ -484,11 +501,11 @@ static pic_status deposit_only(pic_ctx *c, int only) {
   }
   launch_zero_deposit(c->d_inst, c->d_state, c->n_inst, st);
   HIP_TRY(c, launch_particles(c->d_inst, c->d_state, c->n_inst, c->prec, M_DEPOSIT, 256,
-                              particle_grid(c), c->max_n, st));
+                              particle_grid(c, 256), c->max_n, st));
   if (only >= 0 && c->slots[only].cfg.pullback) {
     launch_field(c->d_inst, c->d_state, c->n_inst, 0, st);
     HIP_TRY(c, launch_particles(c->d_inst, c->d_state, c->n_inst, c->prec, M_PULLBACK, 256,
-                                particle_grid(c), c->max_n, st));
+                                particle_grid(c, 256), c->max_n, st));
   }
   if (only >= 0) {
     for (int i = 0; i < c->n_inst; ++i)
@@ -580,7 +597,7 @@ static pic_status enqueue_step(pic_ctx *c, hipStream_t st, bool sort, bool timed
   if (all) { pic_status r = ev_end(c); if (r) return r; }
   if (timed) { pic_status r = ev_begin(c, 1); if (r) return r; }
   HIP_TRY(c, launch_particles(c->d_inst, c->d_state, c->n_inst, c->prec, M_FUSED, c->tune.block,
-                              particle_grid(c), c->max_n, st));
+                              particle_grid(c, c->tune.block), c->max_n, st));
   if (timed) { pic_status r = ev_end(c); if (r) return r; }
   if (all) { pic_status r = ev_begin(c, 3); if (r) return r; }
   HIP_TRY(c, launch_drain(c->d_inst, c->d_state, c->n_inst, c->prec, M_FUSED, drain_grid(c), st));
@@ -746,7 +763,7 @@ pic_status pic_deposit(pic_ctx *c) {
   if (!c) return PIC_EINVAL;
   launch_zero_deposit(c->d_inst, c->d_state, c->n_inst, c->stream);
   HIP_TRY(c, launch_particles(c->d_inst, c->d_state, c->n_inst, c->prec, M_DEPOSIT, 256,
-                              particle_grid(c), c->max_n, c->stream));
+                              particle_grid(c, 256), c->max_n, c->stream));
   c->deposit_current = true;
   return PIC_OK;
 }
@@ -766,7 +783,7 @@ pic_status pic_poisson(pic_ctx *c) {
 pic_status pic_gather_push(pic_ctx *c) {
   if (!c) return PIC_EINVAL;
   HIP_TRY(c, launch_particles(c->d_inst, c->d_state, c->n_inst, c->prec, M_PUSH, 256,
-                              particle_grid(c), c->max_n, c->stream));
+                              particle_grid(c, 256), c->max_n, c->stream));
   HIP_TRY(c, launch_drain(c->d_inst, c->d_state, c->n_inst, c->prec, M_PUSH, drain_grid(c), c->stream));
   c->deposit_current = false;
   return PIC_OK;
@@ -775,7 +792,7 @@ pic_status pic_gather_push(pic_ctx *c) {
 pic_status pic_mcc(pic_ctx *c) {
   if (!c) return PIC_EINVAL;
   HIP_TRY(c, launch_particles(c->d_inst, c->d_state, c->n_inst, c->prec, M_MCC, 256,
-                              particle_grid(c), c->max_n, c->stream));
+                              particle_grid(c, 256), c->max_n, c->stream));
   HIP_TRY(c, launch_drain(c->d_inst, c->d_state, c->n_inst, c->prec, M_MCC, drain_grid(c), c->stream));
   c->deposit_current = false;
   c->host_step++;

@@ -8,6 +8,12 @@ namespace ecpic {
 
 enum Mode : int { M_DEPOSIT = 0, M_PUSH = 1, M_MCC = 2, M_FUSED = 3, M_PULLBACK = 4 };
 
+// Particles per thread of a particle-kernel tile (a tile is block x this),
+// and the tile of the drain and of the sort scatter, in particles or entries.
+constexpr int kParticlesPerThread = 4;
+constexpr int kDrainTile = 256;
+constexpr int kSortTile = 1024;
+
 // Dynamic LDS bytes of the particle kernels for grids of up to max_n cells.
 size_t particle_lds_bytes(int prec, int max_n, int block);
 size_t sort_lds_bytes(int max_n, int prec);

@@ -34,7 +34,7 @@ namespace ecpic {
 constexpr double kHALF_ME_OVER_QE = (0.5 * kME) / kQE;
 constexpr double kTWO_QE_OVER_ME = (2.0 * kQE) / kME;
 constexpr double kTWO_ME_OVER_M = (2.0 * kME) / kMAR;
-constexpr int kPPT = 4;                     // particles per thread per tile (a multiple of 4)
+constexpr int kPPT = kParticlesPerThread;   // particles per thread per tile (a multiple of 4)
 static_assert(kPPT % 4 == 0, "vector loads move 4 particles");
 constexpr float kWalkLimit = 4194304.0f;    // |sigma| beyond 2^22 cells: out of any grid
 
@@ -1216,9 +1216,9 @@ __device__ void drain_one(CInst &I, InstState &S, Smem &sm, int sp, int buf, int
 // Drain the per-segment queues with full wavefronts (k_finalize then closes
 // the pass).
 template <class F, int MODE>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kDrainTile)
 k_drain(const InstDev *__restrict__ insts, InstState *__restrict__ states, int n_inst) {
-  constexpr int BLOCK = 256;
+  constexpr int BLOCK = kDrainTile;   // one queue entry per thread per tile
   __shared__ Smem sm;
   const int t = threadIdx.x;
   if (t < kNctr) sm.ctr[t] = 0;
@@ -1571,15 +1571,15 @@ static hipError_t launch_drain_form(const InstDev *insts, InstState *states, int
                                     int grid, hipStream_t s) {
   switch (mode) {
     case M_PUSH:
-      hipLaunchKernelGGL((k_drain<F, M_PUSH>), dim3(grid), dim3(256), 0, s, insts, states, n_inst);
+      hipLaunchKernelGGL((k_drain<F, M_PUSH>), dim3(grid), dim3(kDrainTile), 0, s, insts, states, n_inst);
       hipLaunchKernelGGL((k_finalize<M_PUSH>), dim3(1), dim3(256), 0, s, insts, states, n_inst);
       break;
     case M_MCC:
-      hipLaunchKernelGGL((k_drain<F, M_MCC>), dim3(grid), dim3(256), 0, s, insts, states, n_inst);
+      hipLaunchKernelGGL((k_drain<F, M_MCC>), dim3(grid), dim3(kDrainTile), 0, s, insts, states, n_inst);
       hipLaunchKernelGGL((k_finalize<M_MCC>), dim3(1), dim3(256), 0, s, insts, states, n_inst);
       break;
     case M_FUSED:
-      hipLaunchKernelGGL((k_drain<F, M_FUSED>), dim3(grid), dim3(256), 0, s, insts, states, n_inst);
+      hipLaunchKernelGGL((k_drain<F, M_FUSED>), dim3(grid), dim3(kDrainTile), 0, s, insts, states, n_inst);
       hipLaunchKernelGGL((k_finalize<M_FUSED>), dim3(1), dim3(256), 0, s, insts, states, n_inst);
       break;
     default:

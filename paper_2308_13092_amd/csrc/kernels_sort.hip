@@ -21,6 +21,7 @@ constexpr int kSB = 256;      // threads per workgroup
 constexpr int kSPPT = 4;      // particles per thread per tile (a multiple of 4)
 static_assert(kSPPT % 4 == 0, "records are loaded 4 at a time");
 constexpr int kSTile = kSB * kSPPT;
+static_assert(kSTile == kSortTile, "the host sizes the sort grid with kSortTile");
 
 struct SortSmem {
   int seg_prefix[2 * kMaxInst + 1];
