@@ -226,6 +226,7 @@ struct pic_ctx {
   InstState *d_state = nullptr;
   unsigned long long *d_diag = nullptr;
   int max_n = 2;
+  int field_classes = 0;   // field_class bits of the used slots
   // 1024 threads per block: measured fastest on the large workload.  Plain
   // launches: on every workload measured they beat graph replay (by about
   // 10 % on the small and resolved discharges, 1 % on the large one).
@@ -275,8 +276,12 @@ static void drop_graphs(pic_ctx *c) {
 // graphs are dropped.
 static void recompute_max_n(pic_ctx *c) {
   int m = 2;
+  c->field_classes = 0;
   for (auto &s : c->slots)
-    if (s.used) m = std::max(m, (int)s.cfg.n_cells);
+    if (s.used) {
+      m = std::max(m, (int)s.cfg.n_cells);
+      c->field_classes |= field_class((int)s.cfg.n_cells);
+    }
   c->max_n = (m + 3) / 4 * 4;
   drop_graphs(c);
 }
@@ -503,7 +508,7 @@ static pic_status deposit_only(pic_ctx *c, int only) {
   HIP_TRY(c, launch_particles(c->d_inst, c->d_state, c->n_inst, c->prec, M_DEPOSIT, 256,
                               particle_grid(c, 256), c->max_n, st));
   if (only >= 0 && c->slots[only].cfg.pullback) {
-    launch_field(c->d_inst, c->d_state, c->n_inst, 0, st);
+    launch_field(c->d_inst, c->d_state, c->n_inst, c->field_classes, 0, st);
     HIP_TRY(c, launch_particles(c->d_inst, c->d_state, c->n_inst, c->prec, M_PULLBACK, 256,
                                 particle_grid(c, 256), c->max_n, st));
   }
@@ -588,7 +593,7 @@ constexpr int64_t kFullTiming = 16;
 static pic_status enqueue_step(pic_ctx *c, hipStream_t st, bool sort, bool timed) {
   const bool all = timed && (c->timed_steps++ % kFullTiming) == 0;
   if (all) { pic_status r = ev_begin(c, 0); if (r) return r; }
-  launch_field(c->d_inst, c->d_state, c->n_inst, 3, st);
+  launch_field(c->d_inst, c->d_state, c->n_inst, c->field_classes, 3, st);
   HIP_TRY(c, hipGetLastError());
   if (any_averaging(c)) {
     launch_moments(c->d_inst, c->d_state, c->n_inst, c->prec, sort_grid(c), c->max_n, st);
@@ -771,7 +776,7 @@ pic_status pic_deposit(pic_ctx *c) {
 pic_status pic_poisson(pic_ctx *c) {
   if (!c) return PIC_EINVAL;
   if (!c->deposit_current) return fail(c, PIC_ESTATE, "deposit is stale: call pic_deposit first");
-  launch_field(c->d_inst, c->d_state, c->n_inst, 1, c->stream);
+  launch_field(c->d_inst, c->d_state, c->n_inst, c->field_classes, 1, c->stream);
   HIP_TRY(c, hipGetLastError());
   if (any_averaging(c)) {
     launch_moments(c->d_inst, c->d_state, c->n_inst, c->prec, sort_grid(c), c->max_n, c->stream);

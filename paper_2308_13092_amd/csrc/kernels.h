@@ -18,7 +18,11 @@ constexpr int kSortTile = 1024;
 size_t particle_lds_bytes(int prec, int max_n, int block);
 size_t sort_lds_bytes(int max_n, int prec);
 
-void launch_field(const InstDev *insts, InstState *states, int n_inst, int mode, hipStream_t s);
+// Field solve of every instance; `classes` says which workgroup sizes the
+// instances need (bit 0: field_class 1, bit 1: field_class 2).
+int field_class(int n_cells);
+void launch_field(const InstDev *insts, InstState *states, int n_inst, int classes, int mode,
+                  hipStream_t s);
 void launch_init(const InstDev *insts, InstState *states, int inst, int species, int prec,
                  double t_ev, int64_t n, hipStream_t s);
 // Persistent pass over every particle of every active instance.

@@ -16,8 +16,11 @@
 
 namespace ecpic {
 
-constexpr int kFB = 1024;           // threads per field workgroup
-constexpr int kFW = kFB / 64;       // its wavefronts
+// Threads per field workgroup: 256 for an instance of at most 512 cells
+// (there the wider workgroup only adds barrier latency), 1024 above.  The
+// choice follows each instance's own grid, never the batch it is in, since
+// the FP64 prefix sums' blocking (and so their rounding) follows it.
+constexpr int kFieldSmallCells = 512;
 
 template <typename T>
 __device__ __forceinline__ T wave_scan_inclusive(T v) {
@@ -37,14 +40,15 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
-// In-place inclusive prefix sum of a[0..n) by the workgroup: each thread sums
-// a contiguous chunk, the chunk totals are scanned within each wavefront with
-// shuffles, then across the wavefronts; the blocking is fixed, so the result
-// is reproducible.  tmp holds kFW values.
-template <typename T>
+// In-place inclusive prefix sum of a[0..n) by the workgroup of FB threads:
+// each thread sums a contiguous chunk, the chunk totals are scanned within
+// each wavefront with shuffles, then across the wavefronts; the blocking is
+// fixed, so the result is reproducible.  tmp holds FB / 64 values.
+template <int FB, typename T>
 __device__ void block_scan_inclusive(T *a, int n, T *tmp) {
+  constexpr int kFW = FB / 64;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int c = (n + kFB - 1) / kFB;
+  const int c = (n + FB - 1) / FB;
   const int lo = min(n, t * c), hi = min(n, lo + c);
   T s = T(0);
   for (int i = lo; i < hi; ++i) { s += a[i]; a[i] = s; }
@@ -62,8 +66,9 @@ __device__ void block_scan_inclusive(T *a, int n, T *tmp) {
   __syncthreads();
 }
 
-template <typename T>
+template <int FB, typename T>
 __device__ T block_sum(T v, T *tmp) {
+  constexpr int kFW = FB / 64;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   v = wave_sum(v);
   if (lane == 0) tmp[w] = v;
@@ -75,7 +80,9 @@ __device__ T block_sum(T v, T *tmp) {
   return r;
 }
 
+template <int FB>
 __device__ double block_max(double v, double *tmp) {
+  constexpr int kFW = FB / 64;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
@@ -90,8 +97,10 @@ __device__ double block_max(double v, double *tmp) {
 
 // mode bit 0: accumulate the averaged profiles when due; bit 1: zero the
 // deposit buffer of step k+1 (for the fused particle pass).
+template <int kFB>
 __global__ void __launch_bounds__(kFB)
 k_field(const InstDev *__restrict__ insts, InstState *__restrict__ states, int mode) {
+  constexpr int kFW = kFB / 64;
   __shared__ int64_t sA[2][kMaxCells + 1];
   __shared__ double sG[kMaxCells + 1];
   __shared__ double sE[kMaxCells + 1];
@@ -103,6 +112,7 @@ k_field(const InstDev *__restrict__ insts, InstState *__restrict__ states, int m
 
   CInst &I = cinst(insts)[blockIdx.x];
   InstState &S = states[blockIdx.x];
+  if ((I.N <= kFieldSmallCells) != (kFB == 256)) return;   // the other launch's instance
   if (!I.active || S.frozen != 0) return;
   if (I.k_stop > 0 && S.k >= I.k_stop) return;
   const int t = threadIdx.x;
@@ -134,7 +144,7 @@ k_field(const InstDev *__restrict__ insts, InstState *__restrict__ states, int m
     for (int n = t; n < N; n += kFB)
       sD[n] = (n == 0) ? 0 : ((nsp > 1) ? (sA[1][n] - sA[0][n]) : sA[0][n]);
     __syncthreads();
-    block_scan_inclusive<int64_t>(sD, N, tmpi);
+    block_scan_inclusive<kFB, int64_t>(sD, N, tmpi);
     for (int n = t; n < N; n += kFB) sG[n] = I.cgauss * (double)sD[n];
     __syncthreads();
   } else {
@@ -142,20 +152,20 @@ k_field(const InstDev *__restrict__ insts, InstState *__restrict__ states, int m
     if (periodic) {
       double part = 0.0;
       for (int n = t; n < N; n += kFB) part += sQ[n];
-      qbg = block_sum<double>(part, tmpd) / I.L;
+      qbg = block_sum<kFB, double>(part, tmpd) / I.L;
     }
     for (int n = t; n < N; n += kFB) {
       const double qn = periodic ? (sQ[n] - qbg * I.V[n]) : sQ[n];
       sG[n] = (n == 0) ? 0.0 : qn / kEPS0;
     }
     __syncthreads();
-    block_scan_inclusive<double>(sG, N, tmpd);
+    block_scan_inclusive<kFB, double>(sG, N, tmpd);
   }
 
   // E_0 from sum_j h_j E_j = phi_0 - phi_N.
   double part = 0.0;
   for (int j = t; j < N; j += kFB) part += sH[j] * sG[j];
-  const double hg = block_sum<double>(part, tmpd);
+  const double hg = block_sum<kFB, double>(part, tmpd);
   const double e0 = (phi0 - phiN - hg) / I.L;
   for (int j = t; j < N; j += kFB) sE[j] = e0 + sG[j];
   __syncthreads();
@@ -163,7 +173,7 @@ k_field(const InstDev *__restrict__ insts, InstState *__restrict__ states, int m
   // phi_j = phi_0 - sum_{i<j} h_i E_i  (reuse sG for the prefix).
   for (int j = t; j < N; j += kFB) sG[j] = sH[j] * sE[j];
   __syncthreads();
-  block_scan_inclusive<double>(sG, N, tmpd);
+  block_scan_inclusive<kFB, double>(sG, N, tmpd);
   for (int n = t; n <= N; n += kFB) {
     double p;
     if (n == 0) p = phi0;
@@ -212,10 +222,10 @@ k_field(const InstDev *__restrict__ insts, InstState *__restrict__ states, int m
   // Field energy and the density maximum (stability monitor 1b).
   double fe = 0.0;
   for (int j = t; j < N; j += kFB) fe += sH[j] * sE[j] * sE[j];
-  fe = block_sum<double>(fe, tmpd);
+  fe = block_sum<kFB, double>(fe, tmpd);
   double nm = 0.0;
   for (int n = t; n <= N; n += kFB) nm = fmax(nm, ((double)sA[0][n] * I.W * 0x1p-32) / I.V[n]);
-  nm = block_max(nm, tmpd);
+  nm = block_max<kFB>(nm, tmpd);
   if (t == 0) {
     S.field_energy = 0.5 * kEPS0 * fe;
     S.ne_max = nm;
@@ -242,8 +252,14 @@ k_field(const InstDev *__restrict__ insts, InstState *__restrict__ states, int m
   }
 }
 
-void launch_field(const InstDev *insts, InstState *states, int n_inst, int mode, hipStream_t s) {
-  hipLaunchKernelGGL(k_field, dim3(n_inst), dim3(kFB), 0, s, insts, states, mode);
+int field_class(int n_cells) { return n_cells <= kFieldSmallCells ? 1 : 2; }
+
+void launch_field(const InstDev *insts, InstState *states, int n_inst, int classes, int mode,
+                  hipStream_t s) {
+  if (classes & 1)
+    hipLaunchKernelGGL(k_field<256>, dim3(n_inst), dim3(256), 0, s, insts, states, mode);
+  if (classes & 2)
+    hipLaunchKernelGGL(k_field<1024>, dim3(n_inst), dim3(1024), 0, s, insts, states, mode);
 }
 
 }  // namespace ecpic
