@@ -1250,39 +1250,55 @@ k_drain(const InstDev *__restrict__ insts, InstState *__restrict__ states, int n
 
 // Close a pass: clear the queues; in the modes that end a step, new
 // particles join the extents, the live count is updated and checked against
-// the growth limit, and k advances.  One workgroup, one thread per instance.
+// the growth limit, and k advances.  One 64-lane workgroup per instance: lane
+// (species << 5 | replica) takes one replica of the step's live and absorbed
+// counts, the halves are summed with shuffles (exact integers), lane 0 closes.
+static_assert(kRep == 32, "one lane per (species, replica)");
 template <int MODE>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(64)
 k_finalize(const InstDev *__restrict__ insts, InstState *__restrict__ states, int n_inst) {
-  for (int i = threadIdx.x; i < n_inst; i += blockDim.x) {
-    CInst &I = cinst(insts)[i];
-    InstState &S = states[i];
-    if (!I.active || S.frozen != 0 || (I.k_stop > 0 && S.k >= I.k_stop)) continue;
-    for (int s = 0; s < I.nsp; ++s) {
-      S.qcount[s] = 0;
-      if (MODE == M_MCC || MODE == M_FUSED) {
-        unsigned long long lv = 0, ab = 0;
-        for (int r = 0; r < kRep; ++r) {
-          lv += S.step_live[s][r];
-          ab += S.step_absorbed[s][r];
-          S.step_live[s][r] = 0;
-          S.step_absorbed[s][r] = 0;
-        }
-        int64_t add = (int64_t)((S.append >> (32 * s)) & 0xFFFFFFFFull);
-        if (S.extent[s] + add > I.cap[s]) add = I.cap[s] - S.extent[s];
-        S.extent[s] += add;
-        const int64_t live = (MODE == M_FUSED) ? ((int64_t)lv - (int64_t)ab + add)
-                                               : (S.n_live[s] - (int64_t)ab + add);
-        S.n_live[s] = live;
-        if ((double)live > I.growth_limit * (double)I.n_init[s] && I.n_init[s] > 0)
-          S.status |= ST_GROWTH;
-      }
+  const int i = blockIdx.x;
+  if (i >= n_inst) return;
+  CInst &I = cinst(insts)[i];
+  InstState &S = states[i];
+  if (!I.active || S.frozen != 0 || (I.k_stop > 0 && S.k >= I.k_stop)) return;
+  constexpr bool ends_step = MODE == M_MCC || MODE == M_FUSED;
+  const int lane = threadIdx.x;
+  unsigned long long lv = 0, ab = 0;
+  if (ends_step) {
+    const int s = lane >> 5, r = lane & 31;
+    if (s < I.nsp) {
+      lv = S.step_live[s][r];
+      ab = S.step_absorbed[s][r];
+      S.step_live[s][r] = 0;
+      S.step_absorbed[s][r] = 0;
     }
-    if (MODE == M_MCC || MODE == M_FUSED) S.append = 0;
-    if (MODE == M_MCC || MODE == M_FUSED) {
-      S.k += 1;
-      if (S.status != 0) S.frozen = 1;
+#pragma unroll
+    for (int o = 16; o > 0; o >>= 1) {
+      lv += __shfl_xor(lv, o, 64);
+      ab += __shfl_xor(ab, o, 64);
     }
+  }
+  const unsigned long long lv_s[2] = {lv, __shfl(lv, 32, 64)};
+  const unsigned long long ab_s[2] = {ab, __shfl(ab, 32, 64)};
+  if (lane != 0) return;
+  for (int s = 0; s < I.nsp; ++s) {
+    S.qcount[s] = 0;
+    if (ends_step) {
+      int64_t add = (int64_t)((S.append >> (32 * s)) & 0xFFFFFFFFull);
+      if (S.extent[s] + add > I.cap[s]) add = I.cap[s] - S.extent[s];
+      S.extent[s] += add;
+      const int64_t live = (MODE == M_FUSED) ? ((int64_t)lv_s[s] - (int64_t)ab_s[s] + add)
+                                             : (S.n_live[s] - (int64_t)ab_s[s] + add);
+      S.n_live[s] = live;
+      if ((double)live > I.growth_limit * (double)I.n_init[s] && I.n_init[s] > 0)
+        S.status |= ST_GROWTH;
+    }
+  }
+  if (ends_step) {
+    S.append = 0;
+    S.k += 1;
+    if (S.status != 0) S.frozen = 1;
   }
 }
 
@@ -1572,15 +1588,15 @@ static hipError_t launch_drain_form(const InstDev *insts, InstState *states, int
   switch (mode) {
     case M_PUSH:
       hipLaunchKernelGGL((k_drain<F, M_PUSH>), dim3(grid), dim3(kDrainTile), 0, s, insts, states, n_inst);
-      hipLaunchKernelGGL((k_finalize<M_PUSH>), dim3(1), dim3(256), 0, s, insts, states, n_inst);
+      hipLaunchKernelGGL((k_finalize<M_PUSH>), dim3(n_inst), dim3(64), 0, s, insts, states, n_inst);
       break;
     case M_MCC:
       hipLaunchKernelGGL((k_drain<F, M_MCC>), dim3(grid), dim3(kDrainTile), 0, s, insts, states, n_inst);
-      hipLaunchKernelGGL((k_finalize<M_MCC>), dim3(1), dim3(256), 0, s, insts, states, n_inst);
+      hipLaunchKernelGGL((k_finalize<M_MCC>), dim3(n_inst), dim3(64), 0, s, insts, states, n_inst);
       break;
     case M_FUSED:
       hipLaunchKernelGGL((k_drain<F, M_FUSED>), dim3(grid), dim3(kDrainTile), 0, s, insts, states, n_inst);
-      hipLaunchKernelGGL((k_finalize<M_FUSED>), dim3(1), dim3(256), 0, s, insts, states, n_inst);
+      hipLaunchKernelGGL((k_finalize<M_FUSED>), dim3(n_inst), dim3(64), 0, s, insts, states, n_inst);
       break;
     default:
       return hipErrorInvalidValue;
