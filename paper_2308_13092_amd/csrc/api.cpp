@@ -219,6 +219,7 @@ struct pic_ctx {
   int n_inst = 0;
   int prec = 0;
   int n_cu = 256;
+  int drain_per_cu[M_PULLBACK + 1] = {1, 1, 1, 1, 1};   // by pass mode
   Pool pool;
   std::vector<SlotHost> slots;
   std::vector<InstDev> host_inst;
@@ -315,7 +316,10 @@ static int particle_grid(const pic_ctx *c, int block) {
   return capped(c, (int64_t)c->n_cu * per, (int64_t)block * kParticlesPerThread);
 }
 static int sort_grid(const pic_ctx *c) { return capped(c, (int64_t)c->n_cu * 4, kSortTile); }
-static int drain_grid(const pic_ctx *c) { return capped(c, (int64_t)c->n_cu * 4, kDrainTile); }
+// The drain grid: every workgroup resident at once, none beyond.
+static int drain_grid(const pic_ctx *c, int mode) {
+  return capped(c, (int64_t)c->n_cu * c->drain_per_cu[mode], kDrainTile);
+}
 
 // Fill InstDev for slot i from its config and block offset; write host arrays.
 static pic_status setup_slot(pic_ctx *c, int i, const pic_config &cfg) {
@@ -605,7 +609,7 @@ static pic_status enqueue_step(pic_ctx *c, hipStream_t st, bool sort, bool timed
                               particle_grid(c, c->tune.block), c->max_n, st));
   if (timed) { pic_status r = ev_end(c); if (r) return r; }
   if (all) { pic_status r = ev_begin(c, 3); if (r) return r; }
-  HIP_TRY(c, launch_drain(c->d_inst, c->d_state, c->n_inst, c->prec, M_FUSED, drain_grid(c), st));
+  HIP_TRY(c, launch_drain(c->d_inst, c->d_state, c->n_inst, c->prec, M_FUSED, drain_grid(c, M_FUSED), st));
   if (all) { pic_status r = ev_end(c); if (r) return r; }
   if (sort) {
     if (timed) { pic_status r = ev_begin(c, 2); if (r) return r; }
@@ -701,6 +705,7 @@ pic_status pic_init(const pic_config *cfgs, int32_t n_inst, void *device_arena, 
     return PIC_EDEVICE;
   }
   c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  for (int m : {M_PUSH, M_MCC, M_FUSED}) c->drain_per_cu[m] = drain_blocks_per_cu(prec, m);
   if (hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking) != hipSuccess) {
     delete c;
     return PIC_EDEVICE;
@@ -789,7 +794,7 @@ pic_status pic_gather_push(pic_ctx *c) {
   if (!c) return PIC_EINVAL;
   HIP_TRY(c, launch_particles(c->d_inst, c->d_state, c->n_inst, c->prec, M_PUSH, 256,
                               particle_grid(c, 256), c->max_n, c->stream));
-  HIP_TRY(c, launch_drain(c->d_inst, c->d_state, c->n_inst, c->prec, M_PUSH, drain_grid(c), c->stream));
+  HIP_TRY(c, launch_drain(c->d_inst, c->d_state, c->n_inst, c->prec, M_PUSH, drain_grid(c, M_PUSH), c->stream));
   c->deposit_current = false;
   return PIC_OK;
 }
@@ -798,7 +803,7 @@ pic_status pic_mcc(pic_ctx *c) {
   if (!c) return PIC_EINVAL;
   HIP_TRY(c, launch_particles(c->d_inst, c->d_state, c->n_inst, c->prec, M_MCC, 256,
                               particle_grid(c, 256), c->max_n, c->stream));
-  HIP_TRY(c, launch_drain(c->d_inst, c->d_state, c->n_inst, c->prec, M_MCC, drain_grid(c), c->stream));
+  HIP_TRY(c, launch_drain(c->d_inst, c->d_state, c->n_inst, c->prec, M_MCC, drain_grid(c, M_MCC), c->stream));
   c->deposit_current = false;
   c->host_step++;
   return PIC_OK;

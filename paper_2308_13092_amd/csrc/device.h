@@ -258,4 +258,57 @@ __device__ __forceinline__ int32_t next_candidate(uint64_t id, int64_t k, int s,
   return geometric((double)(k + 1), u52d(r.x, r.y), nudt);
 }
 
+// ---------------------------------------------------------------------------
+// Persistent grids over concatenated segments (instance x species)
+// ---------------------------------------------------------------------------
+// prefix[1..nseg] hold the segments' tile counts; this turns them into the
+// exclusive prefix (prefix[0] = 0, prefix[nseg] = the total).  Up to 8
+// segments thread 0 sums them; beyond, the first wavefront scans: each lane
+// sums a run of consecutive counts (at most 16 for 512 discharges), the
+// runs' sums are scanned with shuffles, and each lane adds its base back.  Every thread of the workgroup calls it after
+// writing its counts (it synchronises on entry and on exit).
+__device__ inline void tile_prefix(int *prefix, int nseg) {
+  __syncthreads();
+  if (nseg <= 8) {
+    // A few discharges: a serial sum is shorter than the shuffle chain.
+    if (threadIdx.x == 0) {
+      prefix[0] = 0;
+      for (int s = 2; s <= nseg; ++s) prefix[s] += prefix[s - 1];
+    }
+  } else if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    const int per = (nseg + 63) / 64;
+    const int b = 1 + lane * per, e = min(b + per, nseg + 1);
+    int run = 0;
+    for (int s = b; s < e; ++s) {
+      run += prefix[s];
+      prefix[s] = run;
+    }
+    int inc = run;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int v = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += v;
+    }
+    const int base = inc - run;
+    for (int s = b; s < e; ++s) prefix[s] += base;
+    if (lane == 0) prefix[0] = 0;
+  }
+  __syncthreads();
+}
+
+// The segment that holds tile `tile` (< prefix[nseg]): the first s with
+// prefix[s + 1] > tile, by bisection (empty segments are passed over).
+__device__ __forceinline__ int segment_of(const int *prefix, int nseg, int64_t tile) {
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (prefix[mid + 1] <= tile)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
 }  // namespace ecpic

@@ -32,6 +32,9 @@ hipError_t launch_particles(const InstDev *insts, InstState *states, int n_inst,
 // closing kernel (which ends the step in the collision and fused modes).
 hipError_t launch_drain(const InstDev *insts, InstState *states, int n_inst, int prec, int mode,
                         int grid, hipStream_t s);
+// Drain workgroups (of kDrainTile threads) resident on one CU at once, for the
+// given state form and pass mode (M_PUSH, M_MCC or M_FUSED).
+int drain_blocks_per_cu(int prec, int mode);
 hipError_t launch_sort(const InstDev *insts, InstState *states, int n_inst, int prec, int grid,
                        int max_n, hipStream_t s);
 void launch_diag(const InstDev *insts, InstState *states, int inst, int prec,

@@ -597,11 +597,7 @@ __device__ int64_t segment_prefix(const InstDev *insts, const InstState *states,
     const int64_t n = ok ? count_of(S, sp) : 0;
     prefix[s + 1] = (int)((n + tile - 1) / tile);
   }
-  if (t == 0) prefix[0] = 0;
-  __syncthreads();
-  if (t == 0)
-    for (int s = 1; s <= nseg; ++s) prefix[s] += prefix[s - 1];
-  __syncthreads();
+  tile_prefix(prefix, nseg);
   return prefix[nseg];
 }
 
@@ -716,7 +712,7 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
   };
 
   for (int64_t tile = t0; tile < t1; ++tile) {
-    int s = seg < 0 ? 0 : seg;
+    int s = seg < 0 ? segment_of(sm.seg_prefix, 2 * n_inst, tile) : seg;
     while (sm.seg_prefix[s + 1] <= tile) ++s;
     s = __builtin_amdgcn_readfirstlane(s);
     if (s != seg) {
@@ -1156,10 +1152,12 @@ __device__ void drain_one(CInst &I, InstState &S, Smem &sm, int sp, int buf, int
   }
   double ux = vxd, uy = vy, uz = vz;
   bool bound = false;
+  bool scattered;   // a real collision: the velocity changed
   atomicAdd(&sm.ctr[C_CAND + sp], 1ull);
   if (sp == 0) {
     double ej[3];
     const int proc = collide_electron(I, id, k, ux, uy, uz, bound, ej);
+    scattered = proc != 0;
     if (proc) atomicAdd(&sm.ctr[proc == 1 ? C_EL : (proc == 2 ? C_EX : C_IZ)], 1ull);
     if (proc == 3 && I.nsp > 1) {
       const uint4 ch = philox((uint32_t)k, TAG_CHILD, I.seed, id);
@@ -1199,16 +1197,21 @@ __device__ void drain_one(CInst &I, InstState &S, Smem &sm, int sp, int buf, int
       }
     }
   } else {
-    if (collide_ion(I, id, k, ux, uy, uz, bound)) atomicAdd(&sm.ctr[C_CX], 1ull);
+    scattered = collide_ion(I, id, k, ux, uy, uz, bound);
+    if (scattered) atomicAdd(&sm.ctr[C_CX], 1ull);
   }
   if (bound) atomicAdd(&sm.ctr[C_BOUND], 1ull);
-  if constexpr (F::prec == 1) {
-    P.vx[i] = (float)ux;
-    gstore_cold(P.cold + i, Cold32{(float)uy, (float)uz, id});
-  } else {
-    P.vx[i] = ux;
-    P.vy[i] = uy;
-    P.vz[i] = uz;
+  // A null collision leaves the stored velocity as it is: its scattered
+  // single-particle writes (each a partial line in HBM) are skipped.
+  if (scattered) {
+    if constexpr (F::prec == 1) {
+      P.vx[i] = (float)ux;
+      gstore_cold(P.cold + i, Cold32{(float)uy, (float)uz, id});
+    } else {
+      P.vx[i] = ux;
+      P.vy[i] = uy;
+      P.vz[i] = uz;
+    }
   }
   P.knext[i] = next_candidate(id, k, sp, I.seed, I.nudt[sp]);
 }
@@ -1229,7 +1232,7 @@ k_drain(const InstDev *__restrict__ insts, InstState *__restrict__ states, int n
   int seg = -1;
   InstState *Sp = nullptr;
   for (int64_t tile = t0; tile < t1; ++tile) {
-    int s = seg < 0 ? 0 : seg;
+    int s = seg < 0 ? segment_of(sm.seg_prefix, 2 * n_inst, tile) : seg;
     while (sm.seg_prefix[s + 1] <= tile) ++s;
     s = __builtin_amdgcn_readfirstlane(s);
     if (s != seg) {
@@ -1417,11 +1420,7 @@ k_moments(const InstDev *__restrict__ insts, const InstState *__restrict__ state
                     !(I.k_stop > 0 && S.k >= I.k_stop) && I.moments && avg_due(I, S.k);
     prefix[s + 1] = ok ? (int)((S.extent[s & 1] + TILE - 1) / TILE) : 0;
   }
-  if (t == 0) prefix[0] = 0;
-  __syncthreads();
-  if (t == 0)
-    for (int s = 1; s <= nseg; ++s) prefix[s] += prefix[s - 1];
-  __syncthreads();
+  tile_prefix(prefix, nseg);
   const int64_t T = prefix[nseg];
   const int64_t t0 = T * blockIdx.x / gridDim.x, t1 = T * (blockIdx.x + 1) / gridDim.x;
   int seg = -1, N = 0, gather = 0;
@@ -1446,7 +1445,7 @@ k_moments(const InstDev *__restrict__ insts, const InstState *__restrict__ state
     __syncthreads();
   };
   for (int64_t tile = t0; tile < t1; ++tile) {
-    int s = seg < 0 ? 0 : seg;
+    int s = seg < 0 ? segment_of(prefix, nseg, tile) : seg;
     while (prefix[s + 1] <= tile) ++s;
     s = __builtin_amdgcn_readfirstlane(s);
     if (s != seg) {
@@ -1602,6 +1601,26 @@ static hipError_t launch_drain_form(const InstDev *insts, InstState *states, int
       return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+// Drain workgroups that are resident on one CU at once, for the kernel as
+// built (its registers bound it: three 256-thread workgroups per CU).  The
+// persistent grid is sized to exactly that, since workgroups beyond it would
+// run as a partly filled second round after the first.
+template <class F>
+static int drain_resident(int mode) {
+  int n = 0;
+  hipError_t e = hipErrorInvalidValue;
+  if (mode == M_PUSH)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_drain<F, M_PUSH>, kDrainTile, 0);
+  else if (mode == M_MCC)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_drain<F, M_MCC>, kDrainTile, 0);
+  else if (mode == M_FUSED)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_drain<F, M_FUSED>, kDrainTile, 0);
+  return e == hipSuccess && n > 0 ? n : 1;
+}
+int drain_blocks_per_cu(int prec, int mode) {
+  return prec == 1 ? drain_resident<F32>(mode) : drain_resident<F64>(mode);
 }
 
 // The number of queued particles is only known on the device, so the drain

@@ -72,18 +72,14 @@ __device__ __forceinline__ bool key_run(int key, int &len, int &pos) {
 __device__ void seg_prefix_setup(const InstDev *insts, const InstState *states, int n_inst,
                                  int *prefix, int tile = kSTile) {
   const int nseg = 2 * n_inst;
-  for (int s = threadIdx.x; s < nseg; s += blockDim.x) {
+  for (int s = threadIdx.x; s < nseg; s += kSB) {
     CInst &I = cinst(insts)[s >> 1];
     const InstState &S = states[s >> 1];
     const bool ok = I.active && S.frozen == 0 && (s & 1) < I.nsp;
     const int64_t ext = ok ? S.extent[s & 1] : 0;
     prefix[s + 1] = (int)((ext + tile - 1) / tile);
   }
-  if (threadIdx.x == 0) prefix[0] = 0;
-  __syncthreads();
-  if (threadIdx.x == 0)
-    for (int s = 1; s <= nseg; ++s) prefix[s] += prefix[s - 1];
-  __syncthreads();
+  tile_prefix(prefix, nseg);
 }
 
 template <class P>
@@ -148,7 +144,7 @@ k_sort_count(const InstDev *__restrict__ insts, const InstState *__restrict__ st
     __syncthreads();
   };
   for (int64_t tile = t0; tile < t1; ++tile) {
-    int s = seg < 0 ? 0 : seg;
+    int s = seg < 0 ? segment_of(sm.seg_prefix, nseg, tile) : seg;
     while (sm.seg_prefix[s + 1] <= tile) ++s;
     s = __builtin_amdgcn_readfirstlane(s);
     if (s != seg) {
@@ -343,7 +339,7 @@ k_sort_scatter(const InstDev *__restrict__ insts, InstState *__restrict__ states
   P src, dst;
   int64_t ext = 0;
   for (int64_t tile = t0; tile < t1; ++tile) {
-    int s = seg < 0 ? 0 : seg;
+    int s = seg < 0 ? segment_of(sm.seg_prefix, nseg, tile) : seg;
     while (sm.seg_prefix[s + 1] <= tile) ++s;
     s = __builtin_amdgcn_readfirstlane(s);
     if (s != seg) {
