@@ -167,6 +167,15 @@ constexpr int64_t kBytes32 = 32, kBytes64 = 44;
 // they are global memory and would emit FLAT instructions; FLAT operations
 // also count against the LDS wait counter, so every LDS access after a store
 // would wait for that store to reach memory.
+//
+// The vector forms below carry the non-temporal hint: each is used on data
+// that a pass reads or writes once, in whole lines (the streaming pass
+// touches every particle once per step), so those lines stream through L2
+// instead of displacing lines that are reused (the LDS tables' sources, the
+// deposits, the queues).  On the large discharge this took the streaming
+// pass from 0.430 to 0.373 ms.  Single-element stores keep the plain form:
+// their partial lines must merge in L2 (the sort's scatter with the hint took
+// 2.9 ms instead of 1.25).
 #define ECPIC_GLOBAL __attribute__((address_space(1)))
 typedef int ecpic_iv4 __attribute__((ext_vector_type(4)));
 typedef float ecpic_fv4 __attribute__((ext_vector_type(4)));
@@ -180,20 +189,20 @@ __device__ __forceinline__ void gstore(T *p, V v) {
   *(ECPIC_GLOBAL V *)p = v;
 }
 __device__ __forceinline__ int4 gload4(const int *p) {
-  const ecpic_iv4 v = *(const ECPIC_GLOBAL ecpic_iv4 *)p;
+  const ecpic_iv4 v = __builtin_nontemporal_load((const ECPIC_GLOBAL ecpic_iv4 *)p);
   return make_int4(v.x, v.y, v.z, v.w);
 }
 __device__ __forceinline__ float4 gload4(const float *p) {
-  const ecpic_fv4 v = *(const ECPIC_GLOBAL ecpic_fv4 *)p;
+  const ecpic_fv4 v = __builtin_nontemporal_load((const ECPIC_GLOBAL ecpic_fv4 *)p);
   return make_float4(v.x, v.y, v.z, v.w);
 }
 __device__ __forceinline__ double2 gload2(const double *p) {
-  const ecpic_dv2 v = *(const ECPIC_GLOBAL ecpic_dv2 *)p;
+  const ecpic_dv2 v = __builtin_nontemporal_load((const ECPIC_GLOBAL ecpic_dv2 *)p);
   return make_double2(v.x, v.y);
 }
 __device__ __forceinline__ void gstore4(int *p, int a, int b, int c, int d) {
   ecpic_iv4 v = {a, b, c, d};
-  *(ECPIC_GLOBAL ecpic_iv4 *)p = v;
+  __builtin_nontemporal_store(v, (ECPIC_GLOBAL ecpic_iv4 *)p);
 }
 // One particle's cold record as one 16-B load / store.
 __device__ __forceinline__ Cold32 gload_cold(const Cold32 *p) {
@@ -208,11 +217,11 @@ __device__ __forceinline__ void gstore_cold(Cold32 *p, const Cold32 &c) {
 }
 __device__ __forceinline__ void gstore4(float *p, float a, float b, float c, float d) {
   ecpic_fv4 v = {a, b, c, d};
-  *(ECPIC_GLOBAL ecpic_fv4 *)p = v;
+  __builtin_nontemporal_store(v, (ECPIC_GLOBAL ecpic_fv4 *)p);
 }
 __device__ __forceinline__ void gstore2(double *p, double a, double b) {
   ecpic_dv2 v = {a, b};
-  *(ECPIC_GLOBAL ecpic_dv2 *)p = v;
+  __builtin_nontemporal_store(v, (ECPIC_GLOBAL ecpic_dv2 *)p);
 }
 
 // ---------------------------------------------------------------------------
