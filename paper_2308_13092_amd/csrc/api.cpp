@@ -594,10 +594,14 @@ static bool any_averaging(const pic_ctx *c) {
 // one the roofline needs on every step.
 constexpr int64_t kFullTiming = 16;
 
-static pic_status enqueue_step(pic_ctx *c, hipStream_t st, bool sort, bool timed) {
+// One fused step.  close_prev: the previous step was left open and this
+// step's field launch closes it first; leave_open: this step's closing kernel
+// is not launched (the next step's field launch does its work).
+static pic_status enqueue_step(pic_ctx *c, hipStream_t st, bool sort, bool timed,
+                               bool close_prev = false, bool leave_open = false) {
   const bool all = timed && (c->timed_steps++ % kFullTiming) == 0;
   if (all) { pic_status r = ev_begin(c, 0); if (r) return r; }
-  launch_field(c->d_inst, c->d_state, c->n_inst, c->field_classes, 3, st);
+  launch_field(c->d_inst, c->d_state, c->n_inst, c->field_classes, close_prev ? 7 : 3, st);
   HIP_TRY(c, hipGetLastError());
   if (any_averaging(c)) {
     launch_moments(c->d_inst, c->d_state, c->n_inst, c->prec, sort_grid(c), c->max_n, st);
@@ -609,7 +613,8 @@ static pic_status enqueue_step(pic_ctx *c, hipStream_t st, bool sort, bool timed
                               particle_grid(c, c->tune.block), c->max_n, st));
   if (timed) { pic_status r = ev_end(c); if (r) return r; }
   if (all) { pic_status r = ev_begin(c, 3); if (r) return r; }
-  HIP_TRY(c, launch_drain(c->d_inst, c->d_state, c->n_inst, c->prec, M_FUSED, drain_grid(c, M_FUSED), st));
+  HIP_TRY(c, launch_drain(c->d_inst, c->d_state, c->n_inst, c->prec, M_FUSED, drain_grid(c, M_FUSED),
+                          !leave_open, st));
   if (all) { pic_status r = ev_end(c); if (r) return r; }
   if (sort) {
     if (timed) { pic_status r = ev_begin(c, 2); if (r) return r; }
@@ -794,7 +799,7 @@ pic_status pic_gather_push(pic_ctx *c) {
   if (!c) return PIC_EINVAL;
   HIP_TRY(c, launch_particles(c->d_inst, c->d_state, c->n_inst, c->prec, M_PUSH, 256,
                               particle_grid(c, 256), c->max_n, c->stream));
-  HIP_TRY(c, launch_drain(c->d_inst, c->d_state, c->n_inst, c->prec, M_PUSH, drain_grid(c, M_PUSH), c->stream));
+  HIP_TRY(c, launch_drain(c->d_inst, c->d_state, c->n_inst, c->prec, M_PUSH, drain_grid(c, M_PUSH), true, c->stream));
   c->deposit_current = false;
   return PIC_OK;
 }
@@ -803,7 +808,7 @@ pic_status pic_mcc(pic_ctx *c) {
   if (!c) return PIC_EINVAL;
   HIP_TRY(c, launch_particles(c->d_inst, c->d_state, c->n_inst, c->prec, M_MCC, 256,
                               particle_grid(c, 256), c->max_n, c->stream));
-  HIP_TRY(c, launch_drain(c->d_inst, c->d_state, c->n_inst, c->prec, M_MCC, drain_grid(c, M_MCC), c->stream));
+  HIP_TRY(c, launch_drain(c->d_inst, c->d_state, c->n_inst, c->prec, M_MCC, drain_grid(c, M_MCC), true, c->stream));
   c->deposit_current = false;
   c->host_step++;
   return PIC_OK;
@@ -825,11 +830,17 @@ pic_status pic_step(pic_ctx *c, int32_t n_steps) {
     if (r != PIC_OK) return r;
   }
   const int S = c->tune.sort_interval;
+  // With plain launches, a step followed by another in this call (and not
+  // by a sort) is closed by the next step's field launch: one launch fewer
+  // per step.  Every call returns with its last step closed.
+  bool open = false;
   for (int n = 0; n < n_steps; ++n) {
     const bool sort = S > 0 && ((c->host_step + 1) % S) == 0;
     if (c->timing || !c->tune.use_graph) {
-      pic_status r = enqueue_step(c, c->stream, sort, c->timing);
+      const bool leave_open = !sort && n + 1 < n_steps;
+      pic_status r = enqueue_step(c, c->stream, sort, c->timing, open, leave_open);
       if (r != PIC_OK) return r;
+      open = leave_open;
     } else {
       hipGraphExec_t g = nullptr;
       pic_status r = get_graph(c, sort ? 1 : 0, g);

@@ -270,6 +270,63 @@ __device__ __forceinline__ int32_t next_candidate(uint64_t id, int64_t k, int s,
 }
 
 // ---------------------------------------------------------------------------
+// Closing a pass of one instance
+// ---------------------------------------------------------------------------
+// Whether the instance takes part in passes: active, not frozen by an error,
+// and short of its k_stop.
+__device__ __forceinline__ bool pass_open(CInst &I, const InstState &S) {
+  return I.active && S.frozen == 0 && !(I.k_stop > 0 && S.k >= I.k_stop);
+}
+
+// Close a pass: clear the queues; in the passes that end a step (kEndsStep),
+// new particles join the extents, the live count is updated and checked
+// against the growth limit, and k advances.  Called by the 64 lanes of one
+// wavefront for an open instance: lane (species << 5 | replica) takes one
+// replica of the step's live and absorbed counts, the halves are summed with
+// shuffles (exact integers), and lane 0 writes the state.  kFused: the live
+// count comes from the pass's own tally instead of the previous count.
+static_assert(kRep == 32, "one lane per (species, replica)");
+template <bool kEndsStep, bool kFused>
+__device__ inline void close_pass(CInst &I, InstState &S, int lane) {
+  unsigned long long lv = 0, ab = 0;
+  if (kEndsStep) {
+    const int s = lane >> 5, r = lane & 31;
+    if (s < I.nsp) {
+      lv = S.step_live[s][r];
+      ab = S.step_absorbed[s][r];
+      S.step_live[s][r] = 0;
+      S.step_absorbed[s][r] = 0;
+    }
+#pragma unroll
+    for (int o = 16; o > 0; o >>= 1) {
+      lv += __shfl_xor(lv, o, 64);
+      ab += __shfl_xor(ab, o, 64);
+    }
+  }
+  const unsigned long long lv_s[2] = {lv, __shfl(lv, 32, 64)};
+  const unsigned long long ab_s[2] = {ab, __shfl(ab, 32, 64)};
+  if (lane != 0) return;
+  for (int s = 0; s < I.nsp; ++s) {
+    S.qcount[s] = 0;
+    if (kEndsStep) {
+      int64_t add = (int64_t)((S.append >> (32 * s)) & 0xFFFFFFFFull);
+      if (S.extent[s] + add > I.cap[s]) add = I.cap[s] - S.extent[s];
+      S.extent[s] += add;
+      const int64_t live = kFused ? ((int64_t)lv_s[s] - (int64_t)ab_s[s] + add)
+                                  : (S.n_live[s] - (int64_t)ab_s[s] + add);
+      S.n_live[s] = live;
+      if ((double)live > I.growth_limit * (double)I.n_init[s] && I.n_init[s] > 0)
+        S.status |= ST_GROWTH;
+    }
+  }
+  if (kEndsStep) {
+    S.append = 0;
+    S.k += 1;
+    if (S.status != 0) S.frozen = 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Persistent grids over concatenated segments (instance x species)
 // ---------------------------------------------------------------------------
 // prefix[1..nseg] hold the segments' tile counts; this turns them into the

@@ -28,10 +28,12 @@ void launch_init(const InstDev *insts, InstState *states, int inst, int species,
 // Persistent pass over every particle of every active instance.
 hipError_t launch_particles(const InstDev *insts, InstState *states, int n_inst, int prec,
                             int mode, int block, int grid, int max_n, hipStream_t s);
-// Drain of the queued particles of a push / collision pass, then the pass's
-// closing kernel (which ends the step in the collision and fused modes).
+// Drain of the queued particles of a push / collision pass, then, when
+// `close`, the pass's closing kernel (which ends the step in the collision and
+// fused modes).  A fused step left open is closed by the next field launch
+// (mode bit 2).
 hipError_t launch_drain(const InstDev *insts, InstState *states, int n_inst, int prec, int mode,
-                        int grid, hipStream_t s);
+                        int grid, bool close, hipStream_t s);
 // Drain workgroups (of kDrainTile threads) resident on one CU at once, for the
 // given state form and pass mode (M_PUSH, M_MCC or M_FUSED).
 int drain_blocks_per_cu(int prec, int mode);

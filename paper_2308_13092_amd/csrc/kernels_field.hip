@@ -96,7 +96,9 @@ __device__ double block_max(double v, double *tmp) {
 }
 
 // mode bit 0: accumulate the averaged profiles when due; bit 1: zero the
-// deposit buffer of step k+1 (for the fused particle pass).
+// deposit buffer of step k+1 (for the fused particle pass); bit 2: first close
+// the previous fused step (what k_finalize does, when the host did not launch
+// it on its own).
 template <int kFB>
 __global__ void __launch_bounds__(kFB)
 k_field(const InstDev *__restrict__ insts, InstState *__restrict__ states, int mode) {
@@ -110,14 +112,32 @@ k_field(const InstDev *__restrict__ insts, InstState *__restrict__ states, int m
   __shared__ int64_t tmpi[kFW];
   __shared__ double tmpd[kFW];
 
+  __shared__ int64_t s_k;
+  __shared__ int s_open;
+
   CInst &I = cinst(insts)[blockIdx.x];
   InstState &S = states[blockIdx.x];
   if ((I.N <= kFieldSmallCells) != (kFB == 256)) return;   // the other launch's instance
-  if (!I.active || S.frozen != 0) return;
-  if (I.k_stop > 0 && S.k >= I.k_stop) return;
   const int t = threadIdx.x;
+  int64_t k;
+  if (mode & 4) {
+    // The first wavefront closes the previous step; k and whether the
+    // instance is still open reach the workgroup through LDS.
+    if (t < 64) {
+      if (pass_open(I, S)) close_pass<true, true>(I, S, t);
+      if (t == 0) {
+        s_k = S.k;
+        s_open = pass_open(I, S) ? 1 : 0;
+      }
+    }
+    __syncthreads();
+    if (!s_open) return;
+    k = s_k;
+  } else {
+    if (!pass_open(I, S)) return;
+    k = S.k;
+  }
   const int N = I.N;
-  const int64_t k = S.k;
   const int par = (int)(k & 1);
   const bool periodic = I.bc == 1;
   const int nsp = I.nsp;

@@ -1251,12 +1251,7 @@ k_drain(const InstDev *__restrict__ insts, InstState *__restrict__ states, int n
   if (seg >= 0) flush_counters<BLOCK>(sm, Sp, seg & 1);
 }
 
-// Close a pass: clear the queues; in the modes that end a step, new
-// particles join the extents, the live count is updated and checked against
-// the growth limit, and k advances.  One 64-lane workgroup per instance: lane
-// (species << 5 | replica) takes one replica of the step's live and absorbed
-// counts, the halves are summed with shuffles (exact integers), lane 0 closes.
-static_assert(kRep == 32, "one lane per (species, replica)");
+// Close a pass (see close_pass): one 64-lane workgroup per instance.
 template <int MODE>
 __global__ void __launch_bounds__(64)
 k_finalize(const InstDev *__restrict__ insts, InstState *__restrict__ states, int n_inst) {
@@ -1264,45 +1259,8 @@ k_finalize(const InstDev *__restrict__ insts, InstState *__restrict__ states, in
   if (i >= n_inst) return;
   CInst &I = cinst(insts)[i];
   InstState &S = states[i];
-  if (!I.active || S.frozen != 0 || (I.k_stop > 0 && S.k >= I.k_stop)) return;
-  constexpr bool ends_step = MODE == M_MCC || MODE == M_FUSED;
-  const int lane = threadIdx.x;
-  unsigned long long lv = 0, ab = 0;
-  if (ends_step) {
-    const int s = lane >> 5, r = lane & 31;
-    if (s < I.nsp) {
-      lv = S.step_live[s][r];
-      ab = S.step_absorbed[s][r];
-      S.step_live[s][r] = 0;
-      S.step_absorbed[s][r] = 0;
-    }
-#pragma unroll
-    for (int o = 16; o > 0; o >>= 1) {
-      lv += __shfl_xor(lv, o, 64);
-      ab += __shfl_xor(ab, o, 64);
-    }
-  }
-  const unsigned long long lv_s[2] = {lv, __shfl(lv, 32, 64)};
-  const unsigned long long ab_s[2] = {ab, __shfl(ab, 32, 64)};
-  if (lane != 0) return;
-  for (int s = 0; s < I.nsp; ++s) {
-    S.qcount[s] = 0;
-    if (ends_step) {
-      int64_t add = (int64_t)((S.append >> (32 * s)) & 0xFFFFFFFFull);
-      if (S.extent[s] + add > I.cap[s]) add = I.cap[s] - S.extent[s];
-      S.extent[s] += add;
-      const int64_t live = (MODE == M_FUSED) ? ((int64_t)lv_s[s] - (int64_t)ab_s[s] + add)
-                                             : (S.n_live[s] - (int64_t)ab_s[s] + add);
-      S.n_live[s] = live;
-      if ((double)live > I.growth_limit * (double)I.n_init[s] && I.n_init[s] > 0)
-        S.status |= ST_GROWTH;
-    }
-  }
-  if (ends_step) {
-    S.append = 0;
-    S.k += 1;
-    if (S.status != 0) S.frozen = 1;
-  }
+  if (!pass_open(I, S)) return;
+  close_pass<MODE == M_MCC || MODE == M_FUSED, MODE == M_FUSED>(I, S, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1581,24 +1539,20 @@ static hipError_t launch_pk(const InstDev *insts, InstState *states, int n_inst,
   return hipGetLastError();
 }
 
+template <class F, int MODE>
+static void launch_drain_mode(const InstDev *insts, InstState *states, int n_inst, int grid,
+                              bool close, hipStream_t s) {
+  hipLaunchKernelGGL((k_drain<F, MODE>), dim3(grid), dim3(kDrainTile), 0, s, insts, states, n_inst);
+  if (close) hipLaunchKernelGGL((k_finalize<MODE>), dim3(n_inst), dim3(64), 0, s, insts, states, n_inst);
+}
 template <class F>
 static hipError_t launch_drain_form(const InstDev *insts, InstState *states, int n_inst, int mode,
-                                    int grid, hipStream_t s) {
+                                    int grid, bool close, hipStream_t s) {
   switch (mode) {
-    case M_PUSH:
-      hipLaunchKernelGGL((k_drain<F, M_PUSH>), dim3(grid), dim3(kDrainTile), 0, s, insts, states, n_inst);
-      hipLaunchKernelGGL((k_finalize<M_PUSH>), dim3(n_inst), dim3(64), 0, s, insts, states, n_inst);
-      break;
-    case M_MCC:
-      hipLaunchKernelGGL((k_drain<F, M_MCC>), dim3(grid), dim3(kDrainTile), 0, s, insts, states, n_inst);
-      hipLaunchKernelGGL((k_finalize<M_MCC>), dim3(n_inst), dim3(64), 0, s, insts, states, n_inst);
-      break;
-    case M_FUSED:
-      hipLaunchKernelGGL((k_drain<F, M_FUSED>), dim3(grid), dim3(kDrainTile), 0, s, insts, states, n_inst);
-      hipLaunchKernelGGL((k_finalize<M_FUSED>), dim3(n_inst), dim3(64), 0, s, insts, states, n_inst);
-      break;
-    default:
-      return hipErrorInvalidValue;
+    case M_PUSH: launch_drain_mode<F, M_PUSH>(insts, states, n_inst, grid, close, s); break;
+    case M_MCC: launch_drain_mode<F, M_MCC>(insts, states, n_inst, grid, close, s); break;
+    case M_FUSED: launch_drain_mode<F, M_FUSED>(insts, states, n_inst, grid, close, s); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
@@ -1626,9 +1580,9 @@ int drain_blocks_per_cu(int prec, int mode) {
 // The number of queued particles is only known on the device, so the drain
 // grid is fixed and its workgroups split whatever the queues hold.
 hipError_t launch_drain(const InstDev *insts, InstState *states, int n_inst, int prec, int mode,
-                        int grid, hipStream_t s) {
-  if (prec == 1) return launch_drain_form<F32>(insts, states, n_inst, mode, grid, s);
-  return launch_drain_form<F64>(insts, states, n_inst, mode, grid, s);
+                        int grid, bool close, hipStream_t s) {
+  if (prec == 1) return launch_drain_form<F32>(insts, states, n_inst, mode, grid, close, s);
+  return launch_drain_form<F64>(insts, states, n_inst, mode, grid, close, s);
 }
 
 template <class F>
