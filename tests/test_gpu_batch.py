@@ -138,6 +138,23 @@ def test_kernel_timing_changes_nothing(gpu, use_graph):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
+def test_chained_steps_equal_single_steps(gpu, prec):
+    """Within one multi-step call a step's close runs in the next step's field
+    launch; one-step calls close every step with its own kernel.  Both give
+    the same state bitwise, across sorts (every 7 steps here)."""
+    cfgs = [c for c in mixed_configs(prec) if c["n_cells"] > 0][:4]
+    note("chained vs single", prec)
+    a, b = Context()(cfgs), Context()(cfgs)
+    for ctx in (a, b):
+        ctx.set_tuning(use_graph=0, sort_interval=7)
+    a.step(23)
+    for _ in range(23):
+        b.step(1)
+    for i in range(len(cfgs)):
+        assert_same_instance(a, i, b, i)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("block,bpc", [(256, 1), (1024, 0), (512, 5)])
 def test_launch_shape_does_not_change_results(gpu, block, bpc, prec):
     """Small tiles split every species over several workgroups."""
