@@ -185,9 +185,12 @@ typedef struct pic_tuning {
  * step, the sort on every sort, the field and the drain on every 16th timed
  * step (each HIP event costs the stream a few microseconds). */
 typedef struct pic_kernel_time {
-  double field_ms;      int64_t field_launches;     /* Poisson + field (one block per instance) */
+  double field_ms;      int64_t field_launches;     /* Poisson + field (one block per instance);
+                                                       between chained steps also the previous
+                                                       step's close                            */
   double particle_ms;   int64_t particle_launches;  /* streaming pass: gather, push, deposit    */
-  double drain_ms;      int64_t drain_launches;     /* queued particles: collisions, absorption */
+  double drain_ms;      int64_t drain_launches;     /* queued particles: collisions, absorption,
+                                                       and the closing kernel when launched    */
   double sort_ms;       int64_t sort_launches;      /* cell sort + compaction (3 kernels)        */
 } pic_kernel_time;
 

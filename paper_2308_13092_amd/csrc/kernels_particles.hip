@@ -1216,8 +1216,8 @@ __device__ void drain_one(CInst &I, InstState &S, Smem &sm, int sp, int buf, int
   P.knext[i] = next_candidate(id, k, sp, I.seed, I.nudt[sp]);
 }
 
-// Drain the per-segment queues with full wavefronts (k_finalize then closes
-// the pass).
+// Drain the per-segment queues with full wavefronts (close_pass then closes
+// the pass: in k_finalize, or in the next field launch between chained steps).
 template <class F, int MODE>
 __global__ void __launch_bounds__(kDrainTile)
 k_drain(const InstDev *__restrict__ insts, InstState *__restrict__ states, int n_inst) {
