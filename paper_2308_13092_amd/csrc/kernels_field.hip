@@ -43,9 +43,28 @@ __device__ __forceinline__ T wave_sum(T v) {
 // In-place inclusive prefix sum of a[0..n) by the workgroup of FB threads:
 // each thread sums a contiguous chunk, the chunk totals are scanned within
 // each wavefront with shuffles, then across the wavefronts; the blocking is
-// fixed, so the result is reproducible.  tmp holds FB / 64 values.
+// fixed, so the result is reproducible.  tmp holds FB / 64 values.  The
+// 256-thread workgroup (grids of at most 512 cells) scans in its first
+// wavefront alone, in 64 chunks: one barrier instead of three (small
+// discharge 28.2 -> 27.7 us/step).  Callers synchronise before the call.
 template <int FB, typename T>
 __device__ void block_scan_inclusive(T *a, int n, T *tmp) {
+  if constexpr (FB == 256) {
+    if (threadIdx.x < 64) {
+      const int lane = threadIdx.x;
+      const int c = (n + 63) / 64;
+      const int lo = min(n, lane * c), hi = min(n, lo + c);
+      T s = T(0);
+      for (int i = lo; i < hi; ++i) {
+        s += a[i];
+        a[i] = s;
+      }
+      const T base = wave_scan_inclusive(s) - s;
+      for (int i = lo; i < hi; ++i) a[i] += base;
+    }
+    __syncthreads();
+    return;
+  }
   constexpr int kFW = FB / 64;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int c = (n + FB - 1) / FB;
@@ -80,6 +99,31 @@ __device__ T block_sum(T v, T *tmp) {
   return r;
 }
 
+// block_sum of s and block_max of m together: the same per-value arithmetic
+// with one exchange through LDS instead of two.
+template <int FB>
+__device__ void block_sum_max(double &s, double &m, double *tmps, double *tmpm) {
+  constexpr int kFW = FB / 64;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  s = wave_sum(s);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  if (lane == 0) {
+    tmps[w] = s;
+    tmpm[w] = m;
+  }
+  __syncthreads();
+  double rs = 0.0, rm = 0.0;
+#pragma unroll
+  for (int i = 0; i < kFW; ++i) {
+    rs += tmps[i];
+    rm = fmax(rm, tmpm[i]);
+  }
+  __syncthreads();
+  s = rs;
+  m = rm;
+}
+
 template <int FB>
 __device__ double block_max(double v, double *tmp) {
   constexpr int kFW = FB / 64;
@@ -111,6 +155,7 @@ k_field(const InstDev *__restrict__ insts, InstState *__restrict__ states, int m
   __shared__ double sH[kMaxCells + 1];
   __shared__ int64_t tmpi[kFW];
   __shared__ double tmpd[kFW];
+  __shared__ double tmpm[kFW];
 
   __shared__ int64_t s_k;
   __shared__ int s_open;
@@ -142,17 +187,20 @@ k_field(const InstDev *__restrict__ insts, InstState *__restrict__ states, int m
   const bool periodic = I.bc == 1;
   const int nsp = I.nsp;
 
+  // The deposits, and from them (each thread for its own nodes, so without
+  // a barrier in between) Q_n = sum_s (q_s W A_{s,n}) 2^-32 and the integer
+  // Gauss-law differences.
+  const bool int_path = !periodic && I.int_path;
   for (int n = t; n <= N; n += kFB) {
-    sA[0][n] = I.A[par][0][n];
-    sA[1][n] = (nsp > 1) ? I.A[par][1][n] : 0;
+    const int64_t a0 = I.A[par][0][n];
+    const int64_t a1 = (nsp > 1) ? I.A[par][1][n] : 0;
+    sA[0][n] = a0;
+    sA[1][n] = a1;
     if (n < N) sH[n] = I.h[n];
-  }
-  __syncthreads();
-  // Q_n = sum_s (q_s W A_{s,n}) 2^-32.
-  for (int n = t; n <= N; n += kFB) {
-    double q = (I.qW[0] * (double)sA[0][n]) * 0x1p-32;
-    if (nsp > 1) q = q + (I.qW[1] * (double)sA[1][n]) * 0x1p-32;
+    double q = (I.qW[0] * (double)a0) * 0x1p-32;
+    if (nsp > 1) q = q + (I.qW[1] * (double)a1) * 0x1p-32;
     sQ[n] = q;
+    if (int_path && n < N) sD[n] = (n == 0) ? 0 : ((nsp > 1) ? (a1 - a0) : a0);
   }
   __syncthreads();
   const double t_k = (double)k * I.dt;
@@ -160,13 +208,9 @@ k_field(const InstDev *__restrict__ insts, InstState *__restrict__ states, int m
   const double phiN = 0.0;
 
   // G_j, j = 0..N-1 (G_0 = 0).
-  if (!periodic && I.int_path) {
-    for (int n = t; n < N; n += kFB)
-      sD[n] = (n == 0) ? 0 : ((nsp > 1) ? (sA[1][n] - sA[0][n]) : sA[0][n]);
-    __syncthreads();
+  if (int_path) {
     block_scan_inclusive<kFB, int64_t>(sD, N, tmpi);
     for (int n = t; n < N; n += kFB) sG[n] = I.cgauss * (double)sD[n];
-    __syncthreads();
   } else {
     double qbg = 0.0;
     if (periodic) {
@@ -182,16 +226,19 @@ k_field(const InstDev *__restrict__ insts, InstState *__restrict__ states, int m
     block_scan_inclusive<kFB, double>(sG, N, tmpd);
   }
 
-  // E_0 from sum_j h_j E_j = phi_0 - phi_N.
+  // E_0 from sum_j h_j E_j = phi_0 - phi_N.  Each thread reads only the G_j
+  // it wrote (the scan's chunks end with a barrier).
   double part = 0.0;
   for (int j = t; j < N; j += kFB) part += sH[j] * sG[j];
   const double hg = block_sum<kFB, double>(part, tmpd);
   const double e0 = (phi0 - phiN - hg) / I.L;
-  for (int j = t; j < N; j += kFB) sE[j] = e0 + sG[j];
-  __syncthreads();
-
-  // phi_j = phi_0 - sum_{i<j} h_i E_i  (reuse sG for the prefix).
-  for (int j = t; j < N; j += kFB) sG[j] = sH[j] * sE[j];
+  // phi_j = phi_0 - sum_{i<j} h_i E_i  (sG, read before it is overwritten by
+  // the same thread, becomes h_j E_j and then its prefix).
+  for (int j = t; j < N; j += kFB) {
+    const double e = e0 + sG[j];
+    sE[j] = e;
+    sG[j] = sH[j] * e;
+  }
   __syncthreads();
   block_scan_inclusive<kFB, double>(sG, N, tmpd);
   for (int n = t; n <= N; n += kFB) {
@@ -242,10 +289,9 @@ k_field(const InstDev *__restrict__ insts, InstState *__restrict__ states, int m
   // Field energy and the density maximum (stability monitor 1b).
   double fe = 0.0;
   for (int j = t; j < N; j += kFB) fe += sH[j] * sE[j] * sE[j];
-  fe = block_sum<kFB, double>(fe, tmpd);
   double nm = 0.0;
   for (int n = t; n <= N; n += kFB) nm = fmax(nm, ((double)sA[0][n] * I.W * 0x1p-32) / I.V[n]);
-  nm = block_max<kFB>(nm, tmpd);
+  block_sum_max<kFB>(fe, nm, tmpd, tmpm);
   if (t == 0) {
     S.field_energy = 0.5 * kEPS0 * fe;
     S.ne_max = nm;
