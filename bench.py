@@ -211,9 +211,9 @@ def main():
     ap.add_argument("--no-small", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the discharge "
-              f"instances shard across GPUs without any exchange, see the design notes.",
-              file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}). Across GPUs the "
+              f"discharge instances would be split between processes, one per GPU, with no "
+              f"exchange between them; this build measures one GPU.", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2308_13092_amd import configs
