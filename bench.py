@@ -213,7 +213,7 @@ def main():
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}). Across GPUs the "
               f"discharge instances would be split between processes, one per GPU, with no "
-              f"exchange between them; this build measures one GPU.", file=sys.stderr)
+              f"exchange between them; the benchmark measures one GPU.", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2308_13092_amd import configs
