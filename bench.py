@@ -224,8 +224,10 @@ def main():
     print(f"[bench] fp32-state: {r32['value']:.4g} p-s/s, {r32['ms_per_step']:.3f} ms/step, "
           f"live {r32['live']}", file=sys.stderr, flush=True)
     kt = r32["kt"]
+    # The streaming kernel runs once per step; its HIP events bracket a sample
+    # of those launches (every 4th step).
     avg_ms = kt["particle_ms"] / max(kt["particle_launches"], 1)
-    per_launch = r32["particle_steps"] / max(kt["particle_launches"], 1)
+    per_launch = r32["particle_steps"] / a.steps
     achieved = B_ALG[1] * per_launch / (avg_ms * 1e-3) / 1e9
     tr = measured_traffic()
     traffic = None if tr is None else tr["bytes_per_launch"]

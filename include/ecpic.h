@@ -181,9 +181,9 @@ typedef struct pic_tuning {
 } pic_tuning;
 
 /* Kernel timing (pic_kernel_times).  Durations in milliseconds summed over the
- * launches recorded since timing was enabled: the streaming pass on every
- * step, the sort on every sort, the field and the drain on every 16th timed
- * step (each HIP event costs the stream a few microseconds). */
+ * launches recorded since timing was enabled: the streaming pass on every 4th
+ * timed step, the sort on every sort, the field and the drain on every 16th
+ * timed step (each HIP event costs the stream a few microseconds). */
 typedef struct pic_kernel_time {
   double field_ms;      int64_t field_launches;     /* Poisson + field (one block per instance);
                                                        between chained steps also the previous
