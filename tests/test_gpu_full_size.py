@@ -135,3 +135,36 @@ def test_batched_sweep_at_full_size(gpu):
         note("discharge", i, "step", k, [len(st["id"]) for st in states])
         alone.close()
     batch.close()
+
+
+def test_maximum_instance_count(gpu):
+    """PIC_MAX_INSTANCES tiny discharges in one context (1024 segments: the
+    workgroups' tile prefix and segment search at their largest), across a
+    sort: three of them end bitwise as each does alone, and their deposits
+    equal the oracle's deposit of the batch's state."""
+    import inputs
+    from paper_2308_13092_amd import Context
+    n = 512
+    cfgs = [inputs.small_discharge(n_cells=16 + (i % 7) * 8, n_per_species=200 + 37 * (i % 11),
+                                   precision=1, v_rf=100.0 + (i % 5) * 50.0,
+                                   seed=5000 + i, sort_interval=10)
+            for i in range(n)]
+    note("maximum instances", n)
+    batch = Context(cfgs)
+    batch.step(13)
+    for i in (0, 255, n - 1):
+        states = [batch.get_state(i, s) for s in range(2)]
+        f = batch.fields(i)
+        k = int(batch.diagnostics(i)["step"])
+        A = Sim(cfgs[i], species=[species(st, s) for s, st in enumerate(states)], k=k).deposit()
+        assert np.array_equal(f["A_e"], A[0]) and np.array_equal(f["A_i"], A[1]), i
+        alone = Context([cfgs[i]])
+        alone.step(13)
+        for s in range(2):
+            a, b = states[s], alone.get_state(0, s)
+            oa, ob = np.argsort(a["id"]), np.argsort(b["id"])
+            for key in a:
+                assert np.array_equal(a[key][oa], b[key][ob]), (i, s, key)
+        alone.close()
+    batch.close()
+
