@@ -382,13 +382,16 @@ k_sort_scatter(const InstDev *__restrict__ insts, InstState *__restrict__ states
       if (key[q] >= 0 && rank[q] == 0)
         gbase[key[q]] = atomicAdd(&I.scursor[seg & 1][key[q]], (unsigned long long)cnt[key[q]]);
     __syncthreads();
+    // cnt was last read by the reservations above: clear it for the next
+    // tile here, so that the barrier below orders the clearing before the
+    // next tile's rank atomics in every wavefront.
+#pragma unroll
+    for (int q = 0; q < kSPPT; ++q)
+      if (key[q] >= 0 && rank[q] == 0) cnt[key[q]] = 0;
 #pragma unroll
     for (int q = 0; q < kSPPT; ++q)
       if (key[q] >= 0) store_rec(dst, (int64_t)(gbase[key[q]] + rank[q]), r[q]);
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < kSPPT; ++q)
-      if (key[q] >= 0 && rank[q] == 0) cnt[key[q]] = 0;
   }
 }
 
