@@ -241,9 +241,9 @@ def test_sort_interval_does_not_change_results(gpu, prec):
         c = Context()([cfg])
         c.step(30)
         outs.append([c.get_state(0, s) for s in range(2)])
-        if S == 7:
-            d = c.diagnostics()
-            assert d["extent"][0] == d["n_live"][0] or True
+        d = c.diagnostics()
+        for s in range(2):   # dead and new particles since the last sort stay in the extent
+            assert d["extent"][s] >= d["n_live"][s] == len(outs[-1][s]["id"]), (S, s)
     for s in range(2):
         ref = outs[0][s]
         o0 = np.argsort(ref["id"])
@@ -251,6 +251,32 @@ def test_sort_interval_does_not_change_results(gpu, prec):
             o1 = np.argsort(other[s]["id"])
             for k in ref:
                 assert np.array_equal(ref[k][o0], other[s][k][o1]), (s, k)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_sort_keeps_every_particle_in_cell_order(gpu, prec):
+    """An explicit sort after unsorted steps (particles moved, some absorbed,
+    products appended): every live particle is kept once with its values
+    bitwise, the absorbed ones are dropped, and the storage order is by
+    cell."""
+    note("sort keeps particles", prec)
+    cfg = case_cfg(prec, "nonuniform", n=200_000)
+    c = Context()([cfg])
+    c.step(9)
+    before = [c.get_state(0, s) for s in range(2)]
+    c.sort()
+    after = [c.get_state(0, s) for s in range(2)]
+    d = c.diagnostics()
+    nodes = np.asarray(cfg["nodes"], dtype=np.float64)
+    for s in range(2):
+        a, b = before[s], after[s]
+        assert len(b["id"]) == len(a["id"]) == d["n_live"][s] == d["extent"][s]
+        assert len(np.unique(b["id"])) == len(b["id"])
+        oa, ob = np.argsort(a["id"]), np.argsort(b["id"])
+        for k in a:
+            assert np.array_equal(a[k][oa], b[k][ob]), (s, k)
+        cells = b["cell"] if "cell" in b else np.searchsorted(nodes, b["x"], side="right") - 1
+        assert np.all(np.diff(cells) >= 0), s
 
 
 @pytest.mark.parametrize("prec", [0, 1])
