@@ -12,6 +12,7 @@ simulation (they advance k), so callers tune during their warm-up.
 from __future__ import annotations
 
 import itertools
+import sys
 import time
 
 BLOCKS = (256, 512, 1024)
@@ -45,7 +46,7 @@ def autotune(ctx, steps=40, blocks=BLOCKS, blocks_per_cu=BLOCKS_PER_CU,
         sec = _time_steps(ctx, _round_up(steps, S0))
         table.append((dict(block=block, blocks_per_cu=bpc, sort_interval=S0), sec))
         if verbose:
-            print(f"[autotune] block {block} bpc {bpc}: {sec * 1e3:.3f} ms/step", flush=True)
+            print(f"[autotune] block {block} bpc {bpc}: {sec * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
     best = min(table, key=lambda r: r[1])[0]
     # Then the sort interval at that launch shape.
     sort_table = []
@@ -56,7 +57,7 @@ def autotune(ctx, steps=40, blocks=BLOCKS, blocks_per_cu=BLOCKS_PER_CU,
         sec = _time_steps(ctx, _round_up(max(steps, 2 * S), S))
         sort_table.append((dict(best, sort_interval=S), sec))
         if verbose:
-            print(f"[autotune] sort every {S}: {sec * 1e3:.3f} ms/step", flush=True)
+            print(f"[autotune] sort every {S}: {sec * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
     best = min(sort_table, key=lambda r: r[1])[0]
     # Last, graph replay or plain launches at that setting.
     graph_table = []
@@ -66,7 +67,7 @@ def autotune(ctx, steps=40, blocks=BLOCKS, blocks_per_cu=BLOCKS_PER_CU,
         sec = _time_steps(ctx, _round_up(steps, best["sort_interval"] or S0))
         graph_table.append((dict(best, use_graph=g), sec))
         if verbose:
-            print(f"[autotune] use_graph {g}: {sec * 1e3:.3f} ms/step", flush=True)
+            print(f"[autotune] use_graph {g}: {sec * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
     chosen = min(graph_table, key=lambda r: r[1])[0]
     ctx.set_tuning(**chosen)
     return chosen, table + sort_table + graph_table
