@@ -105,6 +105,8 @@ class Sim:
         self.eedf_samples = 0
         self.absorbed = np.zeros((2, 2), dtype=np.int64)      # [species][wall: 0 left, 1 right]
         self.absorbed_energy_ev = np.zeros((2, 2))
+        # the particles absorbed in the last step: (species, wall, energy eV, vx, |v|^2)
+        self.last_absorbed = []
         # impact distributions [species][wall]: energy (bins + overflow), angle
         self.imp_nb = int(c["impact_bins"] or 200)
         self.imp_na = int(c["impact_angle_bins"] or 90)
@@ -262,6 +264,7 @@ class Sim:
 
         survivors = []
         see_new = None
+        self.last_absorbed = []
         for sp in self.sp:
             s = sp.s
             if self.prec == FP64:
@@ -284,6 +287,8 @@ class Sim:
                     v2 = (vxa * vxa + vya * vya) + vza * vza
                     en = (0.5 * self.m[s] / ph.QE) * v2
                     self.absorbed_energy_ev[s, wi] += float(np.sum(en))
+                    if len(en):
+                        self.last_absorbed.append((s, wi, en, vxa, v2))
                     if c["avg_every"] > 0 and k >= c["avg_start"] and len(en):
                         be, ba = impact_bins(en, vxa, v2, self.imp_nb, self.imp_na, self.imp_emax)
                         np.add.at(self.impact_e[s, wi], be, 1)
@@ -374,6 +379,40 @@ class Sim:
         vy = sp.vy.astype(np.float64)
         vz = sp.vz.astype(np.float64)
         return self.W * (0.5 * self.m[s]) * float(np.sum((vx * vx + vy * vy) + vz * vz))
+
+    def monitors(self):
+        """The three stability conditions of Section 1 (Eqs 1a-1c), in the
+        form Section 3a quotes them for a steady state:
+
+        * ne_max: the largest electron density over the nodes of the last
+          solve, n_e,n = W A_e,n 2^-32 / V_n (the deposit of x^k);
+        * wpe_dt_max = omega_pe,max dt with omega_pe^2 = n_e,max e^2 / (eps0 m_e)
+          (condition 1b);
+        * vmax_dt_over_dxmin = max |vx| dt / min h over the electrons of the
+          current state (condition 1c; the fastest particle against the
+          smallest cell);
+        * lambda_de_over_dxmin = lambda_De,min / min h with
+          lambda_De,min = sqrt(eps0 T_e / (n_e,max e)), T_e (in volts) taken as
+          2/3 of the electrons' mean kinetic energy in eV (condition 1a; a
+          reading: the paper does not say which temperature it uses).
+        """
+        g = self.grid
+        A_e = np.asarray(self.A[0], dtype=np.float64)
+        ne = ((A_e * self.W) * TWO_M32) / g.V
+        ne_max = float(ne.max())
+        wpe = math.sqrt(ne_max * ph.QE * ph.QE / (ph.EPS0 * ph.ME))
+        sp = self.sp[0]
+        hmin = float(np.min(g.h))
+        vmax = float(np.max(np.abs(sp.vx.astype(np.float64)))) if sp.n else 0.0
+        vx = sp.vx.astype(np.float64)
+        vy = sp.vy.astype(np.float64)
+        vz = sp.vz.astype(np.float64)
+        mean_ev = float(np.mean(ph.HALF_ME_OVER_QE * ((vx * vx + vy * vy) + vz * vz))) if sp.n else 0.0
+        te = 2.0 * mean_ev / 3.0
+        lde = math.sqrt(ph.EPS0 * te / (ne_max * ph.QE)) if ne_max > 0 else 0.0
+        return dict(ne_max_m3=ne_max, wpe_dt_max=wpe * self.dt,
+                    vmax_dt_over_dxmin=vmax * self.dt / hmin, lambda_de_over_dxmin=lde / hmin,
+                    te_ev=te)
 
     def positions(self, s):
         sp = self.sp[s]
