@@ -11,7 +11,7 @@ particle, and the periodic cell sort.  Throughput = sum over the timed steps
 of the live particles at step start / wall time, with the state resident in
 HBM.  Prints one JSON line.
 
-Beside it: the FP64-form GPU path on the same workload (fewer steps), the
+Beside it: the FP64-form GPU path on the same workload and number of steps, the
 roofline of the dominant kernel (fused particle pass) from HIP-event
 durations over the timed region, and the plain FP64 CPU oracle timed on a
 bounded sample of the same workload on the host.
@@ -84,7 +84,8 @@ def run_gpu(cfg, steps, warmup, autotune=False):
     el = t1 - t0
     out = dict(value=ps / el, ms_per_step=1e3 * el / steps, particle_steps=ps, kt=kt,
                live=[int(v) for v in d1["n_live"]], status=int(d1["status"]),
-               tuning=ctx.tuning())
+               tuning=ctx.tuning(), sorts_in_window=int(kt["sort_launches"]),
+               nu_max=[float(v) for v in d1["nu_max"]])
     ctx.close()
     del ctx
     torch.cuda.empty_cache()
@@ -199,7 +200,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--fp64-steps", type=int, default=500)
+    ap.add_argument("--fp64-steps", type=int, default=0, help="0: as many as --steps")
     ap.add_argument("--particles", type=int, default=32_000_000, help="per species")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
@@ -229,23 +230,40 @@ def main():
     avg_ms = kt["particle_ms"] / max(kt["particle_launches"], 1)
     per_launch = r32["particle_steps"] / a.steps
     achieved = B_ALG[1] * per_launch / (avg_ms * 1e-3) / 1e9
+    # The whole step (field, streaming pass, drain, the share of the sort) at
+    # the same algorithmic bytes per particle-step.
+    step_achieved = B_ALG[1] * r32["value"] / 1e9
     tr = measured_traffic()
     traffic = None if tr is None else tr["bytes_per_launch"]
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                     kernel=f"k_particles<F32, M_FUSED, {r32['tuning']['block']}>", avg_launch_ms=round(avg_ms, 4),
                     particles_per_launch=round(per_launch, 1), bytes_per_particle_step=B_ALG[1],
+                    step_achieved=round(step_achieved, 1), step_frac=round(step_achieved / HBM_PEAK_GBS, 4),
+                    traffic_gbs=(None if traffic is None else round(traffic / (avg_ms * 1e-3) / 1e9, 1)),
                     field_ms_per_launch=round(kt["field_ms"] / max(kt["field_launches"], 1), 4),
                     drain_ms_per_launch=round(kt["drain_ms"] / max(kt["drain_launches"], 1), 4),
-                    sort_ms_per_launch=round(kt["sort_ms"] / max(kt["sort_launches"], 1), 4))
+                    sort_ms_per_launch=round(kt["sort_ms"] / max(kt["sort_launches"], 1), 4),
+                    sorts_in_window=r32["sorts_in_window"])
 
     fp64 = None
     if not a.no_fp64:
         cfg64 = configs.large(n_per_species=a.particles, precision=0)
-        r64 = run_gpu(cfg64, a.fp64_steps, a.warmup)
-        fp64 = dict(value=r64["value"], ms_per_step=r64["ms_per_step"], steps=a.fp64_steps,
-                    fp32_speedup=r32["value"] / r64["value"])
-        print(f"[bench] fp64: {r64['value']:.4g} p-s/s", file=sys.stderr, flush=True)
+        steps64 = a.fp64_steps if a.fp64_steps > 0 else a.steps
+        r64 = run_gpu(cfg64, steps64, a.warmup)
+        kt64 = r64["kt"]
+        avg64 = kt64["particle_ms"] / max(kt64["particle_launches"], 1)
+        k64 = B_ALG[0] * (r64["particle_steps"] / steps64) / (avg64 * 1e-3) / 1e9
+        s64 = B_ALG[0] * r64["value"] / 1e9
+        fp64 = dict(value=r64["value"], ms_per_step=r64["ms_per_step"], steps=steps64,
+                    sorts_in_window=r64["sorts_in_window"], fp32_speedup=r32["value"] / r64["value"],
+                    roofline=dict(bound="hbm", bytes_per_particle_step=B_ALG[0],
+                                  kernel="k_particles<F64, M_FUSED, 1024>", avg_launch_ms=round(avg64, 4),
+                                  achieved=round(k64, 1), frac=round(k64 / HBM_PEAK_GBS, 4),
+                                  step_achieved=round(s64, 1), step_frac=round(s64 / HBM_PEAK_GBS, 4),
+                                  drain_ms_per_launch=round(kt64["drain_ms"] / max(kt64["drain_launches"], 1), 4),
+                                  sort_ms_per_launch=round(kt64["sort_ms"] / max(kt64["sort_launches"], 1), 4)))
+        print(f"[bench] fp64: {r64['value']:.4g} p-s/s, kernel {avg64:.4f} ms", file=sys.stderr, flush=True)
 
     sweep = None
     if not a.no_sweep:
@@ -281,7 +299,7 @@ def main():
                                 f"{a.particles} e- + {a.particles} Ar+, 400 V 13.56 MHz, 20 mTorr, "
                                 f"dt=T_RF/1000, FP32 state, sort every 20"),
                    "particles": 2 * a.particles, "cells": 2048, "state": "fp32",
-                   "tuning": r32["tuning"]},
+                   "tuning": r32["tuning"], "nu_max": r32["nu_max"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fp64_plain": fp64,

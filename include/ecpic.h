@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define PIC_ABI_VERSION 4
+#define PIC_ABI_VERSION 5
 
 typedef struct pic_ctx pic_ctx;  /* opaque; owns host-side metadata only */
 
@@ -150,6 +150,8 @@ typedef struct pic_diag {
   double wpe_dt_max;             /* omega_pe,max dt (stability condition 1b)          */
   double vmax_dt_over_dxmin;     /* max|vx| dt / min h over electrons (condition 1c)   */
   double lambda_de_over_dxmin;   /* sqrt(eps0 T / (n_e,max e)) / min h, T = 2<KE>/3 (1a) */
+  double nu_max[2];              /* null-collision bounds in use [electrons, ions] (1/s):
+                                    the configured values, or those the library computed */
 } pic_diag;
 
 #define PIC_ST_CAPACITY 1

@@ -49,7 +49,7 @@ class pic_diag(C.Structure):
         ("elastic", C.c_int64), ("charge_exchange", C.c_int64), ("candidates", C.c_int64 * 2),
         ("bound_violations", C.c_int64), ("particle_steps", C.c_int64), ("ne_max_m3", C.c_double),
         ("wpe_dt_max", C.c_double), ("vmax_dt_over_dxmin", C.c_double),
-        ("lambda_de_over_dxmin", C.c_double),
+        ("lambda_de_over_dxmin", C.c_double), ("nu_max", C.c_double * 2),
     ]
 
 
@@ -267,6 +267,16 @@ class Context:
                 v = np.array([list(r) if isinstance(r, C.Array) else r for r in v])
             out[name] = v
         out["return_status"] = st
+        return out
+
+    @staticmethod
+    def _diag_dict(d):
+        out = {}
+        for name, _ in pic_diag._fields_:
+            v = getattr(d, name)
+            if isinstance(v, C.Array):
+                v = np.array([list(r) if isinstance(r, C.Array) else r for r in v])
+            out[name] = v
         return out
 
     def get_state(self, inst, species):

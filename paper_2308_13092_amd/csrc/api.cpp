@@ -191,13 +191,16 @@ double lnx_h(double e, double thr, double amp) {
   return amp * std::log(x) / x;
 }
 double nu_max_electron_h(double n_g) {
-  // 1.02 n_g max_eps sum_p sigma_p(eps) v(eps) on a log scan 1e-3 .. 1e5 eV.
+  // 1.02 n_g max_eps sum_p sigma_p(eps) v(eps) on a log scan of 200001 points
+  // from 1e-3 to 1e5 eV: exponents -3 + i (8 / 200000), the last exactly 5.
   double best = 0.0;
   const int n = 200001;
+  const double step = (5.0 - (-3.0)) / (double)(n - 1);
   for (int i = 0; i < n; ++i) {
-    const double e = std::pow(10.0, -3.0 + 8.0 * i / (n - 1));
+    const double y = (i == n - 1) ? 5.0 : (double)i * step + (-3.0);
+    const double e = std::pow(10.0, y);
     const double v = std::sqrt(((2.0 * kQE) / kME) * e);
-    best = std::max(best, (sig_el_h(e) + lnx_h(e, kEXC, 2.7e-20) + lnx_h(e, kION, 7.6e-20)) * v);
+    best = std::max(best, ((sig_el_h(e) + lnx_h(e, kEXC, 2.7e-20)) + lnx_h(e, kION, 7.6e-20)) * v);
   }
   return 1.02 * n_g * best;
 }
@@ -496,8 +499,9 @@ static pic_status setup_slot(pic_ctx *c, int i, const pic_config &cfg) {
   return PIC_OK;
 }
 
-// The other slots must not be touched by the per-slot deposit; the kernels
-// take every active instance, so deactivate the others while it runs.
+// Sort by cell and deposit the new load of one slot (only >= 0) or of all.
+// The other slots must not be touched by the per-slot work; the kernels take
+// every active instance, so deactivate the others while it runs.
 static pic_status deposit_only(pic_ctx *c, int only) {
   hipStream_t st = c->stream;
   std::vector<int> saved(c->n_inst);
@@ -508,6 +512,11 @@ static pic_status deposit_only(pic_ctx *c, int only) {
       HIP_TRY(c, hipMemcpyAsync(&c->d_inst[i].active, &a, sizeof a, hipMemcpyHostToDevice, st));
     }
   }
+  // The initial load is drawn in particle order: one sort leaves it in cell
+  // order, as every later sort does, so the first steps stream sorted state
+  // (on the large discharge the first sort of an unsorted load takes about
+  // five times as long as the later ones).
+  HIP_TRY(c, launch_sort(c->d_inst, c->d_state, c->n_inst, c->prec, sort_grid(c), c->max_n, st));
   launch_zero_deposit(c->d_inst, c->d_state, c->n_inst, st);
   HIP_TRY(c, launch_particles(c->d_inst, c->d_state, c->n_inst, c->prec, M_DEPOSIT, 256,
                               particle_grid(c, 256), c->max_n, st));
@@ -643,6 +652,56 @@ static pic_status get_graph(pic_ctx *c, int which, hipGraphExec_t &out) {
   }
   out = c->graph[which];
   return PIC_OK;
+}
+
+// One instance's diagnostics from its reduction words (D_* layout: live
+// counts, fixed-point kinetic energies, the electrons' max |vx|, deposit
+// totals) and its state.
+static void fill_diag(const pic_ctx *c, int inst, const InstState &S, const unsigned long long *w,
+                      pic_diag *out) {
+  const InstDev &I = c->host_inst[inst];
+  std::memset(out, 0, sizeof *out);
+  out->step = S.k;
+  out->time_s = (double)S.k * I.dt;
+  out->status = S.status;
+  out->n_samples = S.n_samples;
+  out->eedf_samples = S.eedf_samples;
+  auto ctr = [&](int i) {
+    unsigned long long v = 0;
+    for (int r = 0; r < kRep; ++r) v += S.ctr[i][r];
+    return v;
+  };
+  for (int s = 0; s < 2; ++s) {
+    out->n_live[s] = s < I.nsp ? (int64_t)w[D_LIVE0 + s] : 0;
+    out->extent[s] = S.extent[s];
+    out->deposit_total[s] = s < I.nsp ? (int64_t)w[D_DEP0 + s] : 0;
+    out->kinetic_j_m2[s] = I.W * kQE * ((double)w[D_KE0 + s] * 0x1p-20);
+    for (int wl = 0; wl < 2; ++wl) {
+      out->absorbed[s][wl] = (int64_t)ctr(C_ABS + 2 * s + wl);
+      out->absorbed_energy_ev[s][wl] = (double)ctr(C_EABS + 2 * s + wl) / 65536.0;
+    }
+    out->candidates[s] = (int64_t)ctr(C_CAND + s);
+  }
+  out->field_j_m2 = S.field_energy;
+  out->see_emitted = (int64_t)ctr(C_SEE);
+  out->ionisations = (int64_t)ctr(C_IZ);
+  out->excitations = (int64_t)ctr(C_EX);
+  out->elastic = (int64_t)ctr(C_EL);
+  out->charge_exchange = (int64_t)ctr(C_CX);
+  out->bound_violations = (int64_t)ctr(C_BOUND);
+  out->particle_steps = (int64_t)ctr(C_PSTEPS);
+  out->ne_max_m3 = S.ne_max;
+  out->wpe_dt_max = std::sqrt(S.ne_max * kQE * kQE / (kEPS0 * kME)) * I.dt;
+  double vmax;
+  std::memcpy(&vmax, &w[D_VMAX], 8);
+  out->vmax_dt_over_dxmin = vmax * I.dt / I.hmin;
+  const double n_e = (double)out->n_live[0];
+  const double mean_ev = n_e > 0 ? ((double)w[D_KE0] * 0x1p-20) / n_e : 0.0;
+  const double te = 2.0 * mean_ev / 3.0;
+  // lambda_De = sqrt(eps0 T_e / (n_e e)) with T_e in volts.
+  out->lambda_de_over_dxmin = S.ne_max > 0 ? std::sqrt(kEPS0 * te / (S.ne_max * kQE)) / I.hmin : 0.0;
+  out->nu_max[0] = I.nu_max[0];
+  out->nu_max[1] = I.nu_max[1];
 }
 
 // ---------------------------------------------------------------------------
@@ -873,49 +932,13 @@ pic_status pic_diagnostics(pic_ctx *c, int32_t inst, pic_diag *out) {
   const int par = (int)(S.k & 1);
   for (int s = 0; s < I.nsp; ++s)
     HIP_TRY(c, hipMemcpy(A.data() + s * (I.N + 1), I.A[par][s], 8 * (I.N + 1), hipMemcpyDeviceToHost));
-  std::memset(out, 0, sizeof *out);
-  out->step = S.k;
-  out->time_s = (double)S.k * I.dt;
-  out->status = S.status;
-  out->n_samples = S.n_samples;
-  out->eedf_samples = S.eedf_samples;
-  auto ctr = [&](int i) {
-    unsigned long long v = 0;
-    for (int r = 0; r < kRep; ++r) v += S.ctr[i][r];
-    return v;
-  };
-  for (int s = 0; s < 2; ++s) {
-    out->n_live[s] = s < I.nsp ? (int64_t)w[D_LIVE0 + s] : 0;
-    out->extent[s] = S.extent[s];
+  const int upto = (I.bc == PIC_BC_PERIODIC) ? I.N : I.N + 1;
+  for (int s = 0; s < I.nsp; ++s) {
     int64_t tot = 0;
-    const int upto = (I.bc == PIC_BC_PERIODIC) ? I.N : I.N + 1;
     for (int n = 0; n < upto; ++n) tot += A[s * (I.N + 1) + n];
-    out->deposit_total[s] = s < I.nsp ? tot : 0;
-    out->kinetic_j_m2[s] = I.W * kQE * ((double)w[D_KE0 + s] * 0x1p-20);
-    for (int wl = 0; wl < 2; ++wl) {
-      out->absorbed[s][wl] = (int64_t)ctr(C_ABS + 2 * s + wl);
-      out->absorbed_energy_ev[s][wl] = (double)ctr(C_EABS + 2 * s + wl) / 65536.0;
-    }
-    out->candidates[s] = (int64_t)ctr(C_CAND + s);
+    w[D_DEP0 + s] = (unsigned long long)tot;
   }
-  out->field_j_m2 = S.field_energy;
-  out->see_emitted = (int64_t)ctr(C_SEE);
-  out->ionisations = (int64_t)ctr(C_IZ);
-  out->excitations = (int64_t)ctr(C_EX);
-  out->elastic = (int64_t)ctr(C_EL);
-  out->charge_exchange = (int64_t)ctr(C_CX);
-  out->bound_violations = (int64_t)ctr(C_BOUND);
-  out->particle_steps = (int64_t)ctr(C_PSTEPS);
-  out->ne_max_m3 = S.ne_max;
-  out->wpe_dt_max = std::sqrt(S.ne_max * kQE * kQE / (kEPS0 * kME)) * I.dt;
-  double vmax;
-  std::memcpy(&vmax, &w[D_VMAX], 8);
-  out->vmax_dt_over_dxmin = vmax * I.dt / I.hmin;
-  const double n_e = (double)out->n_live[0];
-  const double mean_ev = n_e > 0 ? ((double)w[D_KE0] * 0x1p-20) / n_e : 0.0;
-  const double te = 2.0 * mean_ev / 3.0;
-  // lambda_De = sqrt(eps0 T_e / (n_e e)) with T_e in volts.
-  out->lambda_de_over_dxmin = S.ne_max > 0 ? std::sqrt(kEPS0 * te / (S.ne_max * kQE)) / I.hmin : 0.0;
+  fill_diag(c, inst, S, w, out);
   return status_of(S.status);
 }
 

@@ -46,7 +46,10 @@ void launch_zero_deposit(const InstDev *insts, InstState *states, int n_inst, hi
 void launch_moments(const InstDev *insts, InstState *states, int n_inst, int prec, int grid, int max_n,
                     hipStream_t s);
 
-// Diagnostics reduction output layout (unsigned long long words).
-enum : int { D_LIVE0 = 0, D_LIVE1 = 1, D_KE0 = 2, D_KE1 = 3, D_VMAX = 4, D_NWORDS = 8 };
+// Diagnostics reduction output layout (unsigned long long words): k_diag
+// writes the live counts, kinetic-energy sums and the electrons' max |vx|;
+// the deposit totals (summed on the host).
+enum : int { D_LIVE0 = 0, D_LIVE1 = 1, D_KE0 = 2, D_KE1 = 3, D_VMAX = 4, D_DEP0 = 5, D_DEP1 = 6,
+             D_NWORDS = 8 };
 
 }  // namespace ecpic

@@ -222,11 +222,14 @@ __device__ __forceinline__ int walk_step(const int4 T, int N, int periodic, int 
 }
 
 // A uniform grid is one run without wrap-around ratios: the whole walk is one
-// floor (bounded), or one floor and a wrap (periodic).
+// floor (bounded), or one floor and a wrap (periodic).  A left walk that
+// passes cell 0 of a bounded grid has left it, even when its last step
+// rounds up to the right edge (the carry would bring it back to x = 0).
 __device__ __forceinline__ int walk_uniform(int N, int periodic, int &j, float &sig) {
   const float m = floorf(sig);
   float r = sig - m;
   int jj = j + (int)m;
+  if (!periodic && jj < 0) return W_LEFT;
   if (r >= 1.0f) {
     r = 0.0f;
     jj += 1;
@@ -234,8 +237,6 @@ __device__ __forceinline__ int walk_uniform(int N, int periodic, int &j, float &
   if (periodic) {
     jj %= N;
     if (jj < 0) jj += N;
-  } else if (jj < 0) {
-    return W_LEFT;
   } else if (jj >= N) {
     return W_RIGHT;
   }

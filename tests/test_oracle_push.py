@@ -109,6 +109,47 @@ def closed_form_uniform_walk(sig):
     return shift, out
 
 
+def test_uniform_closed_form_at_the_electrodes_equals_walk_bitwise():
+    """A bounded grid: the closed form leaves at the left electrode when
+    cell + floor(sigma) < 0, before the carry (a left move from x = 0 smaller
+    than half an FP32 ulp rounds sigma + 1 up to 1, but the cell-by-cell walk
+    has already left the grid), and at the right one when the carried cell
+    reaches N."""
+    N = 64
+    g = Grid.make(1.0, N)
+    tiny = [-1e-30, -2.0 ** -30, -2.0 ** -26, -2.0 ** -25, -3 * 2.0 ** -26, -2.0 ** -24, -0.5, -1.0,
+            -1.5, 0.0, 2.0 ** -25, 0.5, 1.0 - 2 ** -24]
+    cells, sigs = [], []
+    for c in (0, 1, 2, N - 2, N - 1):
+        for t in tiny:
+            for o in (0.0, 2.0 ** -24, 1.0 - 2 ** -24):
+                cells.append(c)
+                sigs.append(np.float32(o) + np.float32(t))
+    sig = np.array(sigs, dtype=np.float32)
+    cell0 = np.array(cells, dtype=np.int32)
+    n = len(sig)
+    sp = Species(s=0, prec=FP32, vx=np.zeros(n, np.float32), vy=np.zeros(n, np.float32),
+                 vz=np.zeros(n, np.float32), id=np.arange(n, dtype=np.uint64),
+                 knext=np.zeros(n, np.int64), cell=cell0, off=sig)
+    dtoh, rf, rb = g.walk_tables(0.0)
+    _, cell, off, wall = push_fp32(g, sp, np.zeros(N, np.float32), 0, np.float32(0.0), (dtoh, rf, rb))
+    m = np.floor(sig)
+    jj = cell0.astype(np.int64) + m.astype(np.int64)
+    out = (sig - m).astype(np.float32)
+    left = jj < 0
+    carry = ~left & (out >= np.float32(1.0))
+    out[carry] = np.float32(0.0)
+    jj[carry] += 1
+    right = ~left & (jj >= N)
+    assert np.array_equal(wall == -1, left) and np.array_equal(wall == 1, right)
+    live = wall == 0
+    assert np.array_equal(cell[live].astype(np.int64), jj[live])
+    assert np.array_equal(off[live].view(np.uint32), out[live].view(np.uint32))
+    # the case that needs the order: x = 0 moving left by less than half an ulp
+    k = np.nonzero((cell0 == 0) & (sig < 0) & (sig > -2.0 ** -25))[0]
+    assert len(k) and np.all(wall[k] == -1)
+
+
 def test_uniform_closed_form_equals_walk_bitwise():
     g = Grid.make(1.0, 10 ** 6)  # large enough that nobody leaves
     r = inputs.rng(24)
