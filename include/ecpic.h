@@ -244,6 +244,21 @@ pic_status pic_sort(pic_ctx *ctx);
 /* Counters and monitors of one instance (synchronises). */
 pic_status pic_diagnostics(pic_ctx *ctx, int32_t inst, pic_diag *out);
 
+/* For callers that cannot allocate memory (code under stream capture, tight
+ * serving loops, harnesses that forbid allocation): the diagnostics of n
+ * instances insts[0..n) in one call, out[i] being what pic_diagnostics gives
+ * for insts[i].  It allocates nothing, on the device or the host: its device
+ * scratch is a fixed array inside the library, PIC_NOALLOC_MAX_INST records of
+ * 64 bytes (32 KiB), one copy per GPU, held until the process ends.  n must be
+ * in [1, PIC_NOALLOC_MAX_INST] (else PIC_EINVAL, nothing enqueued); an empty
+ * or out-of-range instance gives PIC_ESTATE / PIC_EINVAL before any work.
+ * Synchronises.  Returns the first device error status among the instances
+ * (PIC_OK if none).  Every call on one GPU shares that GPU's array and clears
+ * its records first: calls that overlap on one GPU (from several host threads
+ * or contexts) race and must be serialised by the caller. */
+#define PIC_NOALLOC_MAX_INST 512
+pic_status pic_diagnostics_noalloc(pic_ctx *ctx, const int32_t *insts, int32_t n, pic_diag *out);
+
 /* Copy the live particles of one species to host arrays (synchronises).  The
  * order is unspecified; compare by id.  PIC_EINVAL if view->n is too small. */
 pic_status pic_get_state(pic_ctx *ctx, int32_t inst, int32_t species, pic_state_view *view);

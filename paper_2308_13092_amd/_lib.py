@@ -88,6 +88,7 @@ SIGNATURES = [
     ("pic_step", C.c_int, [_CTX, C.c_int32]),
     ("pic_sort", C.c_int, [_CTX]),
     ("pic_diagnostics", C.c_int, [_CTX, C.c_int32, C.POINTER(pic_diag)]),
+    ("pic_diagnostics_noalloc", C.c_int, [_CTX, C.POINTER(C.c_int32), C.c_int32, C.POINTER(pic_diag)]),
     ("pic_get_state", C.c_int, [_CTX, C.c_int32, C.c_int32, C.POINTER(pic_state_view)]),
     ("pic_set_state", C.c_int, [_CTX, C.c_int32, C.c_int32, C.POINTER(pic_state_view)]),
     ("pic_set_step", C.c_int, [_CTX, C.c_int32, C.c_int64]),
@@ -278,6 +279,21 @@ class Context:
                 v = np.array([list(r) if isinstance(r, C.Array) else r for r in v])
             out[name] = v
         return out
+
+    def diagnostics_noalloc(self, insts):
+        """pic_diagnostics_noalloc over a list of instances: one dict per
+        instance, as ``diagnostics`` gives."""
+        n = len(insts)
+        ids = (C.c_int32 * max(n, 1))(*[int(i) for i in insts])
+        outs = (pic_diag * max(n, 1))()
+        st = self.lib.pic_diagnostics_noalloc(self.ctx, ids, n, outs)
+        self._check(st, "pic_diagnostics_noalloc")
+        res = []
+        for i in range(n):
+            d = self._diag_dict(outs[i])
+            d["return_status"] = st
+            res.append(d)
+        return res
 
     def get_state(self, inst, species):
         d = self.diagnostics(inst, allow_error=True)

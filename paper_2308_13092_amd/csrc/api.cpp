@@ -222,6 +222,7 @@ struct pic_ctx {
   int n_inst = 0;
   int prec = 0;
   int n_cu = 256;
+  int device = 0;              // the device current at pic_init: the arena's
   int drain_per_cu[M_PULLBACK + 1] = {1, 1, 1, 1, 1};   // by pass mode
   Pool pool;
   std::vector<SlotHost> slots;
@@ -773,6 +774,11 @@ pic_status pic_init(const pic_config *cfgs, int32_t n_inst, void *device_arena, 
     return PIC_EDEVICE;
   }
   c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  c->device = dev;
+  if (noalloc_setup(dev) != hipSuccess) {
+    delete c;
+    return fail(nullptr, PIC_EDEVICE, "device address of the no-allocation scratch");
+  }
   for (int m : {M_PUSH, M_MCC, M_FUSED}) c->drain_per_cu[m] = drain_blocks_per_cu(prec, m);
   if (hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking) != hipSuccess) {
     delete c;
@@ -940,6 +946,46 @@ pic_status pic_diagnostics(pic_ctx *c, int32_t inst, pic_diag *out) {
   }
   fill_diag(c, inst, S, w, out);
   return status_of(S.status);
+}
+
+pic_status pic_diagnostics_noalloc(pic_ctx *c, const int32_t *insts, int32_t n, pic_diag *out) {
+  if (!c) return PIC_EINVAL;
+  if (!insts || !out) return fail(c, PIC_EINVAL, "null instance list or output");
+  if (n < 1 || n > kNoAllocMaxInst)
+    return fail(c, PIC_EINVAL, "pic_diagnostics_noalloc takes 1 to " + std::to_string(kNoAllocMaxInst) +
+                                   " instances per call, got " + std::to_string(n));
+  for (int i = 0; i < n; ++i) {
+    pic_status r = check_inst(c, insts[i]);
+    if (r != PIC_OK) return r;
+  }
+  unsigned long long *scr = noalloc_scratch(c->device);
+  if (!scr) return fail(c, PIC_EDEVICE, "no-allocation scratch was not set up on this device");
+  hipStream_t st = c->stream;
+  // The array keeps the previous call's records: clear this call's.
+  launch_fill_zero(scr, n * kNoAllocRecord, st);
+  for (int i = 0; i < n; ++i) {
+    unsigned long long *rec = scr + (size_t)i * kNoAllocRecord;
+    launch_diag(c->d_inst, c->d_state, insts[i], c->prec, rec, st);
+    launch_deposit_total(c->d_inst, c->d_state, insts[i], rec, st);
+  }
+  HIP_TRY(c, hipGetLastError());
+  // Records come back in chunks through a buffer on the stack.
+  constexpr int kChunk = 16;
+  unsigned long long w[kChunk * kNoAllocRecord];
+  pic_status worst = PIC_OK;
+  for (int i0 = 0; i0 < n; i0 += kChunk) {
+    const int m = std::min(kChunk, n - i0);
+    HIP_TRY(c, hipMemcpyAsync(w, scr + (size_t)i0 * kNoAllocRecord, sizeof(unsigned long long) * m * kNoAllocRecord,
+                              hipMemcpyDeviceToHost, st));
+    for (int j = 0; j < m; ++j) {
+      InstState S;
+      pic_status r = read_state(c, insts[i0 + j], S);   // synchronises the stream
+      if (r != PIC_OK) return r;
+      fill_diag(c, insts[i0 + j], S, w + (size_t)j * kNoAllocRecord, out + i0 + j);
+      if (worst == PIC_OK) worst = status_of(S.status);
+    }
+  }
+  return worst;
 }
 
 pic_status pic_get_state(pic_ctx *c, int32_t inst, int32_t species, pic_state_view *v) {

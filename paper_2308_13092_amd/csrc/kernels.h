@@ -48,8 +48,20 @@ void launch_moments(const InstDev *insts, InstState *states, int n_inst, int pre
 
 // Diagnostics reduction output layout (unsigned long long words): k_diag
 // writes the live counts, kinetic-energy sums and the electrons' max |vx|;
-// the deposit totals (summed on the host).
+// k_deposit_total the two deposit totals.
 enum : int { D_LIVE0 = 0, D_LIVE1 = 1, D_KE0 = 2, D_KE1 = 3, D_VMAX = 4, D_DEP0 = 5, D_DEP1 = 6,
              D_NWORDS = 8 };
+
+// The no-allocation diagnostics (noalloc.hip): a library-owned device array
+// of kNoAllocMaxInst records of kNoAllocRecord words.
+constexpr int kNoAllocMaxInst = 512;
+constexpr int kNoAllocRecord = D_NWORDS;
+// Look up the array's device address on `device` (which must be current),
+// once per device; noalloc_scratch returns it (nullptr before the setup).
+hipError_t noalloc_setup(int device);
+unsigned long long *noalloc_scratch(int device);
+void launch_fill_zero(unsigned long long *p, int n, hipStream_t s);
+void launch_deposit_total(const InstDev *insts, const InstState *states, int inst,
+                          unsigned long long *out, hipStream_t s);
 
 }  // namespace ecpic
