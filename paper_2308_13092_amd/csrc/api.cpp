@@ -129,7 +129,8 @@ GridLayout layout(const pic_config &c) {
   g.impact = take(8 * 4 * impact_row(c));
   for (int s = 0; s < 2; ++s) g.scount[s] = take(8 * n1);
   for (int s = 0; s < 2; ++s) g.scursor[s] = take(8 * n1);
-  for (int s = 0; s < 2; ++s) g.queue[s] = take((s == 0 || c.n_species != 1) ? 4 * (size_t)eff_cap(c) : 0);
+  // queue records of 16 B, at most one per particle and pass
+  for (int s = 0; s < 2; ++s) g.queue[s] = take((s == 0 || c.n_species != 1) ? 16 * (size_t)eff_cap(c) : 0);
   g.particles = o;
   const int nsp = c.n_species == 1 ? 1 : 2;
   o += (size_t)nsp * 2 * align_up((size_t)eff_cap(c) * bytes_per_particle(c.precision));
@@ -466,7 +467,7 @@ static pic_status setup_slot(pic_ctx *c, int i, const pic_config &cfg) {
   for (int s = 0; s < 2; ++s) {
     I.scount[s] = (unsigned long long *)(base + g.scount[s]);
     I.scursor[s] = (unsigned long long *)(base + g.scursor[s]);
-    I.queue[s] = (int *)(base + g.queue[s]);
+    I.queue[s] = (int4 *)(base + g.queue[s]);
   }
   const size_t pb = align_up((size_t)cap * bytes_per_particle(cfg.precision));
   for (int s = 0; s < I.nsp; ++s)
@@ -1004,10 +1005,11 @@ pic_status pic_get_state(pic_ctx *c, int32_t inst, int32_t species, pic_state_vi
   int64_t live = 0;
   if (c->prec == PIC_FP32_STATE) {
     P32 P = view32(b, cap);
+    std::vector<uint32_t> hw(ext);
     std::vector<int32_t> cell(ext);
     std::vector<float> off(ext), vx(ext), vy(ext), vz(ext);
     std::vector<Cold32> cold(ext);
-    HIP_TRY(c, hipMemcpy(cell.data(), P.cell, 4 * ext, hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(hw.data(), P.hw, 4 * ext, hipMemcpyDeviceToHost));
     HIP_TRY(c, hipMemcpy(off.data(), P.off, 4 * ext, hipMemcpyDeviceToHost));
     HIP_TRY(c, hipMemcpy(vx.data(), P.vx, 4 * ext, hipMemcpyDeviceToHost));
     HIP_TRY(c, hipMemcpy(kn.data(), P.knext, 4 * ext, hipMemcpyDeviceToHost));
@@ -1016,6 +1018,9 @@ pic_status pic_get_state(pic_ctx *c, int32_t inst, int32_t species, pic_state_vi
       vy[i] = cold[i].vy;
       vz[i] = cold[i].vz;
       id[i] = cold[i].id;
+      // the hot word's cell and candidacy (absolute step)
+      cell[i] = hw_live(hw[i]) ? hw_cell(hw[i]) : -1;
+      if (hw_live(hw[i])) kn[i] = (int32_t)hw_knext(hw[i], kn[i], S.k);
     }
     for (int64_t i = 0; i < ext; ++i) live += cell[i] >= 0;
     if (live > v->n) { v->n = live; return fail(c, PIC_EINVAL, "view too small"); }
@@ -1092,7 +1097,9 @@ pic_status pic_set_state(pic_ctx *c, int32_t inst, int32_t species, const pic_st
   if (n > 0) {
     if (c->prec == PIC_FP32_STATE) {
       P32 P = view32(b, cap);
-      HIP_TRY(c, hipMemcpy(P.cell, v->cell, 4 * n, hipMemcpyHostToDevice));
+      std::vector<uint32_t> hw(n);
+      for (int64_t i = 0; i < n; ++i) hw[i] = hw_encode(v->cell[i], v->knext[i], S.k);
+      HIP_TRY(c, hipMemcpy(P.hw, hw.data(), 4 * n, hipMemcpyHostToDevice));
       HIP_TRY(c, hipMemcpy(P.off, v->off, 4 * n, hipMemcpyHostToDevice));
       HIP_TRY(c, hipMemcpy(P.vx, v->vx, 4 * n, hipMemcpyHostToDevice));
       HIP_TRY(c, hipMemcpy(P.knext, v->knext, 4 * n, hipMemcpyHostToDevice));
@@ -1125,6 +1132,12 @@ pic_status pic_set_step(pic_ctx *c, int32_t inst, int64_t k) {
   InstState S;
   r = read_state(c, inst, S);
   if (r != PIC_OK) return r;
+  if (c->prec == PIC_FP32_STATE && k != S.k) {
+    // the FP32 countdowns count from the step: re-express them
+    launch_reencode(c->d_inst, c->d_state, inst, S.k, k, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
   S.k = k;
   HIP_TRY(c, hipMemcpy(c->d_state + inst, &S, sizeof S, hipMemcpyHostToDevice));
   c->deposit_current = false;

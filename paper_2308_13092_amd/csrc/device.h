@@ -9,12 +9,14 @@
 // Particles are stored as structure-of-arrays, each field a contiguous array
 // of `cap` elements (cap is a multiple of 64, so every array is 256-B
 // aligned):
-//   FP32-state form: cell i32 | off f32 | vx f32 | knext i32 | {vy f32, vz f32, id u64}
-//   FP64 form:       x f64    | vx f64  | vy f64 | vz f64 | knext i32 | id u64
-// (the FP32 form keeps the fields the streaming pass never reads in one 16-B
-// record per particle).
+//   FP32-state form: hw u32 | off f32 | vx f32 | knext i32 | {vy f32, vz f32, id u64}
+//   FP64 form:       x f64  | vx f64  | vy f64 | vz f64 | knext i32 | id u64
+// The FP32 form's hot word hw holds the cell and the steps left until the
+// particle's next collision candidacy (see hw_encode), so the streaming pass
+// reads 12 bytes per particle and writes 12; the fields it never reads sit in
+// one 16-B record per particle.
 // A dead (absorbed) particle keeps its slot until the next sort with
-// cell = -1 (FP32) or x = -1 (FP64).
+// hw = kHwDead (FP32) or x = -1 (FP64).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -90,7 +92,7 @@ struct InstDev {
   double imp_escale, imp_ascale;  // bins / emax (1/eV), angle bins / 90 (1/deg)
   int moments;                    // accumulate accM1, accM2, accP on the averaged steps
   unsigned long long *scount[2], *scursor[2];
-  int *queue[2];               // per-species queue of particles for the drain kernel
+  int4 *queue[2];              // per-species queue of particles for the drain kernel (QRec)
   // particles
   char *pbuf[2][2];            // [species][buffer]
 };
@@ -127,25 +129,64 @@ struct InstState {
 };
 
 // ---------------------------------------------------------------------------
+// The FP32 form's hot word
+// ---------------------------------------------------------------------------
+// bits 0-11  cell (0xFFF: dead slot; grids have at most 2048 cells)
+// bits 12-30 countdown c: steps from the current step k to the particle's next
+//            collision candidacy, knext = k + c
+// bit  31    far: knext lies beyond the countdown's range (or before k); the
+//            knext array then holds it and c counts down towards a re-check
+// A candidate is a particle with c = 0 at its step (after a re-check of the
+// knext array when far).  Every pass that advances k decrements c, so the
+// countdown needs no read of the knext array.
+constexpr uint32_t kHwDead = 0xFFFFFFFFu;
+constexpr uint32_t kHwCell = 0xFFFu;
+constexpr int kHwShift = 12;
+constexpr uint32_t kCntMax = (1u << 19) - 1u;
+constexpr uint32_t kHwFar = 1u << 31;
+__host__ __device__ inline int hw_cell(uint32_t w) { return (int)(w & kHwCell); }
+__host__ __device__ inline bool hw_live(uint32_t w) { return (w & kHwCell) != kHwCell; }
+__host__ __device__ inline uint32_t hw_cnt(uint32_t w) { return (w >> kHwShift) & kCntMax; }
+__host__ __device__ inline bool hw_far(uint32_t w) { return (w & kHwFar) != 0u; }
+// The hot word of a particle in `cell` whose next candidacy is step knext,
+// seen from step k.
+__host__ __device__ inline uint32_t hw_encode(int cell, int64_t knext, int64_t k) {
+  const int64_t w = knext - k;
+  if (w >= 0 && w <= (int64_t)kCntMax) return (uint32_t)cell | ((uint32_t)w << kHwShift);
+  return (uint32_t)cell | ((w < 0 ? 0u : kCntMax) << kHwShift) | kHwFar;
+}
+// The particle's next candidacy (far_knext: its entry of the knext array).
+__host__ __device__ inline int64_t hw_knext(uint32_t w, int32_t far_knext, int64_t k) {
+  return hw_far(w) ? (int64_t)far_knext : k + (int64_t)hw_cnt(w);
+}
+// The same word in another cell, one step later (the countdown of a
+// particle that is not a candidate moves one step closer).
+__host__ __device__ inline uint32_t hw_advance(uint32_t w, int cell, bool count) {
+  const uint32_t dec = (count && hw_cnt(w) != 0u) ? (1u << kHwShift) : 0u;
+  return ((w & ~kHwCell) - dec) | (uint32_t)cell;
+}
+
+// ---------------------------------------------------------------------------
 // Particle buffer views
 // ---------------------------------------------------------------------------
-// FP32 form: the fields every step streams (cell, off, vx, knext) are
-// separate arrays; the ones only collisions, emission, diagnostics and the
-// sort touch (vy, vz, id) form one 16-B record per particle, so that handling
-// a single particle costs one memory line for them instead of three.
+// FP32 form: the fields every step streams (hw, off, vx) are separate
+// arrays; the ones only collisions, emission, diagnostics and the sort touch
+// (vy, vz, id) form one 16-B record per particle, so that handling a single
+// particle costs one memory line for them instead of three.  knext is read
+// only for far particles (see hw_encode).
 struct Cold32 {
   float vy, vz;
   uint64_t id;
 };
 struct P32 {
-  int32_t *cell; float *off, *vx; int32_t *knext; Cold32 *cold;
+  uint32_t *hw; float *off, *vx; int32_t *knext; Cold32 *cold;
 };
 struct P64 {
   double *x, *vx, *vy, *vz; int32_t *knext; uint64_t *id;
 };
 __host__ __device__ inline P32 view32(char *b, int64_t cap) {
   P32 p;
-  p.cell = reinterpret_cast<int32_t *>(b);
+  p.hw = reinterpret_cast<uint32_t *>(b);
   p.off = reinterpret_cast<float *>(b + 4 * cap);
   p.vx = reinterpret_cast<float *>(b + 8 * cap);
   p.knext = reinterpret_cast<int32_t *>(b + 12 * cap);
@@ -206,6 +247,15 @@ __device__ __forceinline__ void gstore4(int *p, int a, int b, int c, int d) {
   ecpic_iv4 v = {a, b, c, d};
   __builtin_nontemporal_store(v, (ECPIC_GLOBAL ecpic_iv4 *)p);
 }
+// One 16-B queue record (plain: the drain's records are read once, in order).
+__device__ __forceinline__ int4 gload_rec(const int4 *p) {
+  const ecpic_iv4 v = *(const ECPIC_GLOBAL ecpic_iv4 *)p;
+  return make_int4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void gstore_rec(int4 *p, const int4 &r) {
+  ecpic_iv4 v = {r.x, r.y, r.z, r.w};
+  *(ECPIC_GLOBAL ecpic_iv4 *)p = v;
+}
 // One particle's cold record as one 16-B load / store.
 __device__ __forceinline__ Cold32 gload_cold(const Cold32 *p) {
   const ecpic_iv4 v = *(const ECPIC_GLOBAL ecpic_iv4 *)p;
@@ -224,6 +274,26 @@ __device__ __forceinline__ void gstore4(float *p, float a, float b, float c, flo
 __device__ __forceinline__ void gstore2(double *p, double a, double b) {
   ecpic_dv2 v = {a, b};
   __builtin_nontemporal_store(v, (ECPIC_GLOBAL ecpic_dv2 *)p);
+}
+
+// ---------------------------------------------------------------------------
+// Values that are the same on every lane, made known as such to the compiler
+// (they then live in scalar registers).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uni(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ int64_t uni(int64_t v) {
+  const int lo = __builtin_amdgcn_readfirstlane((int)(v & 0xFFFFFFFFll));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+}
+__device__ __forceinline__ double uni(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xFFFFFFFFll));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
 // ---------------------------------------------------------------------------

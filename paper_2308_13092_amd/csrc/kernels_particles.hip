@@ -38,21 +38,6 @@ constexpr int kPPT = kParticlesPerThread;   // particles per thread per tile (a 
 static_assert(kPPT % 4 == 0, "vector loads move 4 particles");
 constexpr float kWalkLimit = 4194304.0f;    // |sigma| beyond 2^22 cells: out of any grid
 
-// ---------------------------------------------------------------------------
-// Values that are the same on every lane, made known as such to the compiler
-// (they then live in scalar registers).
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ float uni(float v) {
-  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
-}
-__device__ __forceinline__ double uni(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xFFFFFFFFll));
-  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
-  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
-
 // The grid parameters that locating and walking a particle need.  The
 // streaming kernel reads them once per segment into registers: read through
 // the instance table inside the particle loop they would be reloaded from
@@ -507,22 +492,26 @@ struct F64 {
 };
 
 // Write a new particle (SEE electron or ionisation product).
+// k1: the first step the particle takes part in; kn: its first candidacy.
 template <class F>
 __device__ void write_new(CInst &I, typename F::View P, int64_t idx, double x, int cell,
-                         float off, double vx, double vy, double vz, uint64_t id, int32_t kn) {
+                         float off, double vx, double vy, double vz, uint64_t id, int32_t kn,
+                         int64_t k1) {
   if constexpr (F::prec == 1) {
-    P.cell[idx] = cell;
+    const uint32_t w = hw_encode(cell, kn, k1);
+    P.hw[idx] = w;
     P.off[idx] = off;
     P.vx[idx] = (float)vx;
     gstore_cold(P.cold + idx, Cold32{(float)vy, (float)vz, id});
+    if (hw_far(w)) P.knext[idx] = kn;
   } else {
     P.x[idx] = x;
     P.vx[idx] = vx;
     P.vy[idx] = vy;
     P.vz[idx] = vz;
     P.id[idx] = id;
+    P.knext[idx] = kn;
   }
-  P.knext[idx] = kn;
 }
 
 // Secondary emission by an ion absorbed at `wall` during step k.  The new
@@ -556,7 +545,7 @@ __device__ void emit_secondary(CInst &I, InstState &S, Smem &sm, uint64_t ion_id
   }
   const int64_t idx = append_slot(I, S, 0);
   if (idx < 0) return;
-  write_new<F>(I, F::view(I, 0, buf), idx, x, cell, off, vx, I.vt_see * zy, I.vt_see * zz, cid, kn);
+  write_new<F>(I, F::view(I, 0, buf), idx, x, cell, off, vx, I.vt_see * zy, I.vt_see * zz, cid, kn, k + 1);
   atomicAdd(&sm.ctr[C_SEE], 1ull);
   if (dep) global_deposit(I, A_next_e, j, xi);
 }
@@ -574,10 +563,14 @@ __device__ void emit_secondary(CInst &I, InstState &S, Smem &sm, uint64_t ion_id
 // collision arithmetic and ionisation products.  Keeping the rare, heavy code
 // out of the streaming kernel keeps its register footprint small.
 // ---------------------------------------------------------------------------
-// Queue entry: particle index | kind << 30; kind 0 = collision candidate,
-// 1 / 2 = absorbed at the left / right electrode, 3 = non-finite state.
-constexpr int kSpill = 256;   // entries moved to HBM per reservation
-constexpr int kWaveQ = 320;   // per-wavefront LDS queue: kSpill - 1 carried + 64 new entries fit
+// Queue record (16 B): word 0 = particle index | kind << 30 (kind 0 =
+// collision candidate, 1 / 2 = absorbed at the left / right electrode,
+// 3 = non-finite state); then the particle's state as the pass leaves it,
+// FP32 form: its hot word, vx and offset (as bits); FP64 form: 0 and vx (as
+// two words).  The drain so reads none of the streamed arrays, only the
+// particle's cold record (and, for far candidates, its knext).
+constexpr int kSpill = 128;   // records moved to HBM per reservation
+constexpr int kWaveQ = 192;   // per-wavefront LDS queue: kSpill - 1 carried + 64 new records fit
 static_assert(kSpill - 1 + 64 <= kWaveQ, "wavefront queue too small");
 constexpr int kQShift = 30;
 constexpr int kQMask = (1 << kQShift) - 1;
@@ -641,7 +634,7 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
   double *sNodes = sE64 + np1 + 1;
   const size_t tables = (F::prec == 1) ? a_bytes + (size_t)max_n * 16 + (size_t)(np1 + 1) * 4
                                        : (size_t)np1 * 24 + 8;
-  int *wq = reinterpret_cast<int *>(dsm + ((tables + 15) & ~(size_t)15)) + (t >> 6) * kWaveQ;
+  int4 *wq = reinterpret_cast<int4 *>(dsm + ((tables + 15) & ~(size_t)15)) + (t >> 6) * kWaveQ;
   int wq_n = 0;   // entries in this wavefront's queue (wavefront-uniform)
 
   if (t < kNctr) sm.ctr[t] = 0;
@@ -659,7 +652,7 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
   int64_t k = 0, ext = 0, seg_first = 0;
   typename F::View P;
   int64_t *A_out = nullptr;
-  int *gq = nullptr;
+  int4 *gq = nullptr;
   bool deposit_on = false;
   unsigned long long live_here = 0;
   // Per-segment constants, in scalar registers (see GridPar).
@@ -674,9 +667,9 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
   // segment's HBM queue.  The reservation is an atomic on the segment's one
   // counter, which every wavefront of the device shares: chunks keep those
   // same-address atomics (which serialise) few.
-  auto enqueue = [&](bool want, int entry) {
+  auto enqueue = [&](bool want, int4 rec) {
     const unsigned long long m = __ballot(want);
-    if (want) wq[wq_n + __popcll(m & lt_mask)] = entry;
+    if (want) wq[wq_n + __popcll(m & lt_mask)] = rec;
     wq_n += __popcll(m);
   };
   auto spill = [&](bool all) {
@@ -685,7 +678,7 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
     unsigned long long b = 0;
     if (lane == 0) b = atomicAdd(&Sp->qcount[sp], (unsigned long long)n);
     b = __shfl(b, 0, 64);
-    for (int e = lane; e < n; e += 64) gstore<int>(gq + b + e, wq[wq_n - n + e]);
+    for (int e = lane; e < n; e += 64) gstore_rec(gq + b + e, wq[wq_n - n + e]);
     wq_n -= n;
   };
   auto flush = [&]() {
@@ -724,9 +717,12 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
       sp = seg & 1;
       CInst &I = *Ip;
       N = I.N;
-      k = Sp->k;
-      ext = Sp->extent[sp];
-      seg_first = sm.seg_prefix[seg];
+      // Per-segment values in scalar registers: read into vector registers,
+      // every tile would wait at the loop's join for all outstanding memory
+      // operations (the previous tile's stores included) before its loads.
+      k = uni((int64_t)Sp->k);
+      ext = uni((int64_t)Sp->extent[sp]);
+      seg_first = uni((int64_t)sm.seg_prefix[seg]);
       P = F::view(I, sp, Sp->parity);
       gq = I.queue[sp];
       const int par = (int)(k & 1);
@@ -784,24 +780,19 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
 
     if constexpr (F::prec == 1) {
       // ---------------- FP32-state form ----------------
-      int c[kPPT], kn[kPPT];
+      // hw: hot word (cell, countdown to the next candidacy, far flag)
+      uint32_t hw[kPPT];
       float o[kPPT], vx[kPPT];
       if (full) {
 #pragma unroll
         for (int g = 0; g < kPPT; g += 4) {
-          const int4 c4 = gload4(P.cell + i0 + g);
-          c[g] = c4.x; c[g + 1] = c4.y; c[g + 2] = c4.z; c[g + 3] = c4.w;
-          if (MODE != M_MCC) {
-            const float4 o4 = gload4(P.off + i0 + g);
-            o[g] = o4.x; o[g + 1] = o4.y; o[g + 2] = o4.z; o[g + 3] = o4.w;
-          }
-          if (MODE != M_DEPOSIT && MODE != M_MCC) {
+          const int4 h4 = gload4(reinterpret_cast<const int *>(P.hw) + i0 + g);
+          hw[g] = (uint32_t)h4.x; hw[g + 1] = (uint32_t)h4.y; hw[g + 2] = (uint32_t)h4.z; hw[g + 3] = (uint32_t)h4.w;
+          const float4 o4 = gload4(P.off + i0 + g);
+          o[g] = o4.x; o[g + 1] = o4.y; o[g + 2] = o4.z; o[g + 3] = o4.w;
+          if (MODE != M_DEPOSIT) {
             const float4 v4 = gload4(P.vx + i0 + g);
             vx[g] = v4.x; vx[g + 1] = v4.y; vx[g + 2] = v4.z; vx[g + 3] = v4.w;
-          }
-          if (MODE == M_MCC || MODE == M_FUSED) {
-            const int4 k4 = gload4(P.knext + i0 + g);
-            kn[g] = k4.x; kn[g + 1] = k4.y; kn[g + 2] = k4.z; kn[g + 3] = k4.w;
           }
         }
       } else {
@@ -809,27 +800,26 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
         for (int q = 0; q < kPPT; ++q) {
           const int64_t i = i0 + q;
           const bool v = i < ext;
-          c[q] = v ? gload<int>(P.cell + i) : -1;
+          hw[q] = v ? gload<uint32_t>(P.hw + i) : kHwDead;
           o[q] = v ? gload<float>(P.off + i) : 0.0f;
           vx[q] = v ? gload<float>(P.vx + i) : 0.0f;
-          kn[q] = v ? gload<int>(P.knext + i) : 0;
         }
       }
-      int cn[kPPT];
+      uint32_t hn[kPPT];
       float on[kPPT], vn[kPPT];
       if constexpr (MODE == M_PUSH || MODE == M_FUSED) {
         // Gather, push and first walk step of the thread's particles; then
         // the rare walks that go on (across more than one run boundary).
-        int st[kPPT];
+        int cn[kPPT], st[kPPT];
         bool more = false;
 #pragma unroll
         for (int q = 0; q < kPPT; ++q) {
-          cn[q] = c[q];
+          const int j = hw_cell(hw[q]);
+          cn[q] = j;
           on[q] = o[q];
           vn[q] = vx[q];
           st[q] = W_IN;
-          if (c[q] < 0) continue;
-          const int j = c[q];
+          if (!hw_live(hw[q])) continue;
           const float e = (gather == 0)   ? sE32[j]
                           : (gather == 1) ? ((1.0f - o[q]) * sE32[j]) + (o[q] * sE32[j + 1])
                                           : gather_ec2_32(sE32, j, o[q]);
@@ -868,16 +858,19 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
         }
 #pragma unroll
         for (int q = 0; q < kPPT; ++q) {
-          const bool live = c[q] >= 0;
+          const bool live = hw_live(hw[q]);
           const int ii = (int)(i0 + q);
           const int wall = st[q];
           const float v1 = vn[q];
           const bool gone = live && (wall != W_IN || v1 != v1);   // absorbed or non-finite
-          const bool cand = MODE == M_FUSED && live && !gone && coll && kn[q] <= k;
+          // a candidate this step: countdown at zero (the drain re-checks far ones)
+          const bool cand = MODE == M_FUSED && live && !gone && coll && hw_cnt(hw[q]) == 0u;
           live_here += live ? 1u : 0u;
           want[q] = gone || cand;
           went[q] = qentry(ii, gone ? ((wall == W_BAD || v1 != v1) ? 3 : (wall < 0 ? 1 : 2)) : 0);
-          cn[q] = gone ? -1 : cn[q];
+          // the countdown moves one step in the fused pass (the drain rewrites
+          // a candidate's word)
+          hn[q] = !live ? hw[q] : (gone ? kHwDead : hw_advance(hw[q], cn[q], MODE == M_FUSED && coll));
           on[q] = gone ? o[q] : on[q];
           if (live && !gone) {
             const int jj = cn[q];
@@ -904,52 +897,64 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
       for (int q = 0; q < kPPT; ++q) {
         want[q] = false;
         went[q] = 0;
-        cn[q] = c[q];
+        hn[q] = hw[q];
         on[q] = o[q];
         vn[q] = vx[q];
-        if (c[q] < 0) continue;   // dead slot
+        if (!hw_live(hw[q])) continue;   // dead slot
         const int ii = (int)(i0 + q);
+        const int j = hw_cell(hw[q]);
         if constexpr (MODE == M_DEPOSIT) {
           if (gather == 2) {
-            lds_deposit_s2(sA, G, c[q], (double)o[q]);
+            lds_deposit_s2(sA, G, j, (double)o[q]);
           } else {
             int64_t w0, w1;
             weights32(o[q], w0, w1);
-            dep.add(sA, c[q], w0, w1);
+            dep.add(sA, j, w0, w1);
           }
         } else if constexpr (MODE == M_PULLBACK) {
-          const float e = (gather == 0)   ? sE32[c[q]]
-                          : (gather == 1) ? ((1.0f - o[q]) * sE32[c[q]]) + (o[q] * sE32[c[q] + 1])
-                                          : gather_ec2_32(sE32, c[q], o[q]);
+          const float e = (gather == 0)   ? sE32[j]
+                          : (gather == 1) ? ((1.0f - o[q]) * sE32[j]) + (o[q] * sE32[j + 1])
+                                          : gather_ec2_32(sE32, j, o[q]);
           vn[q] = vx[q] - hq32 * e;
         } else if constexpr (MODE == M_MCC) {
-          want[q] = coll && kn[q] <= k;
+          want[q] = coll && hw_cnt(hw[q]) == 0u;
           went[q] = qentry(ii, 0);
+          hn[q] = hw_advance(hw[q], j, coll);
         }
       }
       }
       if constexpr (MODE == M_DEPOSIT || MODE == M_FUSED) dep.flush(sA);
-      if constexpr (MODE == M_PUSH || MODE == M_FUSED || MODE == M_PULLBACK) {
+      if constexpr (MODE == M_PUSH || MODE == M_FUSED || MODE == M_PULLBACK || MODE == M_MCC) {
         if (full) {
 #pragma unroll
           for (int g = 0; g < kPPT; g += 4) {
-            if constexpr (MODE != M_PULLBACK) {
-              gstore4(P.cell + i0 + g, cn[g], cn[g + 1], cn[g + 2], cn[g + 3]);
+            if constexpr (MODE != M_PULLBACK)
+              gstore4(reinterpret_cast<int *>(P.hw) + i0 + g, (int)hn[g], (int)hn[g + 1], (int)hn[g + 2],
+                      (int)hn[g + 3]);
+            if constexpr (MODE == M_PUSH || MODE == M_FUSED)
               gstore4(P.off + i0 + g, on[g], on[g + 1], on[g + 2], on[g + 3]);
-            }
-            gstore4(P.vx + i0 + g, vn[g], vn[g + 1], vn[g + 2], vn[g + 3]);
+            if constexpr (MODE != M_MCC) gstore4(P.vx + i0 + g, vn[g], vn[g + 1], vn[g + 2], vn[g + 3]);
           }
         } else {
 #pragma unroll
           for (int q = 0; q < kPPT; ++q) {
             const int64_t i = i0 + q;
             if (i < ext) {
-              if constexpr (MODE != M_PULLBACK) {
-                gstore<int>(P.cell + i, cn[q]);
-                gstore<float>(P.off + i, on[q]);
-              }
-              gstore<float>(P.vx + i, vn[q]);
+              if constexpr (MODE != M_PULLBACK) gstore<uint32_t>(P.hw + i, hn[q]);
+              if constexpr (MODE == M_PUSH || MODE == M_FUSED) gstore<float>(P.off + i, on[q]);
+              if constexpr (MODE != M_MCC) gstore<float>(P.vx + i, vn[q]);
             }
+          }
+        }
+      }
+      // The queued particles, each with the state this pass leaves it in
+      // (the drain then reads none of the streamed arrays).
+      if constexpr (MODE == M_PUSH || MODE == M_MCC || MODE == M_FUSED) {
+        if (__ballot(want[0] || want[1] || want[2] || want[3]) != 0) {
+#pragma unroll
+          for (int q = 0; q < kPPT; ++q) {
+            enqueue(want[q], make_int4(went[q], (int)hn[q], __float_as_int(vn[q]), __float_as_int(on[q])));
+            spill(false);   // at most 64 more: kSpill - 1 + 64 <= kWaveQ
           }
         }
       }
@@ -963,7 +968,7 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
           const double2 xa = gload2(P.x + i0 + g);
           const double2 xb = gload2(P.x + i0 + g + 2);
           x[g] = xa.x; x[g + 1] = xa.y; x[g + 2] = xb.x; x[g + 3] = xb.y;
-          if (MODE != M_DEPOSIT && MODE != M_MCC) {
+          if (MODE != M_DEPOSIT) {
             const double2 va = gload2(P.vx + i0 + g);
             const double2 vb = gload2(P.vx + i0 + g + 2);
             vx[g] = va.x; vx[g + 1] = va.y; vx[g + 2] = vb.x; vx[g + 3] = vb.y;
@@ -1077,13 +1082,15 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
           }
         }
       }
-    }
-    if constexpr (MODE == M_PUSH || MODE == M_MCC || MODE == M_FUSED) {
-      if (__ballot(want[0] || want[1] || want[2] || want[3]) != 0) {
+      // The queued particles with their velocity after this pass.
+      if constexpr (MODE == M_PUSH || MODE == M_MCC || MODE == M_FUSED) {
+        if (__ballot(want[0] || want[1] || want[2] || want[3]) != 0) {
 #pragma unroll
-        for (int q = 0; q < kPPT; ++q) {
-          enqueue(want[q], went[q]);   // at most 64 more: kSpill - 1 + 64 <= kWaveQ
-          spill(false);
+          for (int q = 0; q < kPPT; ++q) {
+            const long long vb = __double_as_longlong(vn[q]);
+            enqueue(want[q], make_int4(went[q], 0, (int)(vb & 0xFFFFFFFFll), (int)(vb >> 32)));
+            spill(false);   // at most 64 more: kSpill - 1 + 64 <= kWaveQ
+          }
         }
       }
     }
@@ -1106,18 +1113,19 @@ __device__ __forceinline__ void record_impact(CInst &I, int sp, int wi, double e
   atomicAdd(&row[nb + 1 + ba], 1ull);
 }
 
-// Velocity and id of particle i.
-__device__ __forceinline__ void load_particle(const P32 &P, int64_t i, double &vx, double &vy,
-                                              double &vz, uint64_t &id) {
+// Velocity and id of a queued particle: vx from its queue record, the rest
+// from its cold record.
+__device__ __forceinline__ void load_particle(const P32 &P, int64_t i, const int4 &rec, double &vx,
+                                              double &vy, double &vz, uint64_t &id) {
   const Cold32 c = gload_cold(P.cold + i);
-  vx = (double)gload<float>(P.vx + i);
+  vx = (double)__int_as_float(rec.z);
   vy = (double)c.vy;
   vz = (double)c.vz;
   id = c.id;
 }
-__device__ __forceinline__ void load_particle(const P64 &P, int64_t i, double &vx, double &vy,
-                                              double &vz, uint64_t &id) {
-  vx = P.vx[i];
+__device__ __forceinline__ void load_particle(const P64 &P, int64_t i, const int4 &rec, double &vx,
+                                              double &vy, double &vz, uint64_t &id) {
+  vx = __longlong_as_double(((long long)rec.w << 32) | (long long)(uint32_t)rec.z);
   vy = P.vy[i];
   vz = P.vz[i];
   id = P.id[i];
@@ -1128,7 +1136,8 @@ __device__ __forceinline__ void load_particle(const P64 &P, int64_t i, double &v
 // step).  Products go straight into the deposit of step k+1 in the fused pass.
 template <class F, int MODE>
 __device__ void drain_one(CInst &I, InstState &S, Smem &sm, int sp, int buf, int64_t k,
-                          typename F::View P, int entry) {
+                          typename F::View P, const int4 rec) {
+  const int entry = rec.x;
   const int64_t i = entry & kQMask;
   const int kind = (int)((unsigned)entry >> kQShift);
   if (kind == 3) {
@@ -1136,9 +1145,21 @@ __device__ void drain_one(CInst &I, InstState &S, Smem &sm, int sp, int buf, int
     atomicAdd(&sm.ctr[C_NONFINITE], 1ull);
     return;
   }
+  if constexpr (F::prec == 1) {
+    // A far particle whose countdown ran out before its candidacy: only its
+    // countdown is renewed (it is not a candidate).
+    const uint32_t hw = (uint32_t)rec.y;
+    if (kind == 0 && hw_far(hw)) {
+      const int32_t kf = P.knext[i];
+      if ((int64_t)kf > k) {
+        P.hw[i] = hw_encode(hw_cell(hw), kf, k + 1);
+        return;
+      }
+    }
+  }
   double vxd, vy, vz;
   uint64_t id;
-  load_particle(P, i, vxd, vy, vz, id);
+  load_particle(P, i, rec, vxd, vy, vz, id);
   if (kind != 0) {
     const int wi = kind - 1;
     atomicAdd(&sm.ctr[C_ABS + 2 * sp + wi], 1ull);
@@ -1172,17 +1193,17 @@ __device__ void drain_one(CInst &I, InstState &S, Smem &sm, int sp, int buf, int
       float oo = 0.0f;
       double xx = 0.0;
       if constexpr (F::prec == 1) {
-        cc = P.cell[i];
-        oo = P.off[i];
+        cc = hw_cell((uint32_t)rec.y);
+        oo = __int_as_float(rec.w);
       } else {
         xx = P.x[i];
       }
       if (ie >= 0)
         write_new<F>(I, P, ie, xx, cc, oo, ej[0], ej[1], ej[2], eid,
-                     next_candidate(eid, k, 0, I.seed, I.nudt[0]));
+                     next_candidate(eid, k, 0, I.seed, I.nudt[0]), k + 1);
       if (ii >= 0)
         write_new<F>(I, F::view(I, 1, buf), ii, xx, cc, oo, gx, gy, gz, iid,
-                     next_candidate(iid, k, 1, I.seed, I.nudt[1]));
+                     next_candidate(iid, k, 1, I.seed, I.nudt[1]), k + 1);
       if constexpr (MODE == M_FUSED) {
         int j;
         double xi;
@@ -1214,7 +1235,14 @@ __device__ void drain_one(CInst &I, InstState &S, Smem &sm, int sp, int buf, int
       P.vz[i] = uz;
     }
   }
-  P.knext[i] = next_candidate(id, k, sp, I.seed, I.nudt[sp]);
+  const int32_t kn = next_candidate(id, k, sp, I.seed, I.nudt[sp]);
+  if constexpr (F::prec == 1) {
+    const uint32_t w = hw_encode(hw_cell((uint32_t)rec.y), kn, k + 1);
+    P.hw[i] = w;
+    if (hw_far(w)) P.knext[i] = kn;
+  } else {
+    P.knext[i] = kn;
+  }
 }
 
 // Drain the per-segment queues with full wavefronts (close_pass then closes
@@ -1232,6 +1260,9 @@ k_drain(const InstDev *__restrict__ insts, InstState *__restrict__ states, int n
   const int64_t t1 = T * (blockIdx.x + 1) / gridDim.x;
   int seg = -1;
   InstState *Sp = nullptr;
+  // per-segment values, in scalar registers
+  int64_t qn = 0, k = 0, first = 0;
+  int buf = 0;
   for (int64_t tile = t0; tile < t1; ++tile) {
     int s = seg < 0 ? segment_of(sm.seg_prefix, 2 * n_inst, tile) : seg;
     while (sm.seg_prefix[s + 1] <= tile) ++s;
@@ -1240,14 +1271,15 @@ k_drain(const InstDev *__restrict__ insts, InstState *__restrict__ states, int n
       if (seg >= 0) flush_counters<BLOCK>(sm, Sp, seg & 1);
       seg = s;
       Sp = &states[seg >> 1];
+      qn = uni((int64_t)Sp->qcount[seg & 1]);
+      k = uni((int64_t)Sp->k);
+      buf = uni(Sp->parity);
+      first = uni((int64_t)sm.seg_prefix[seg]);
     }
     CInst &I = cinst(insts)[seg >> 1];
     const int sp = seg & 1;
-    const int64_t e = (tile - sm.seg_prefix[seg]) * BLOCK + t;
-    if (e < (int64_t)Sp->qcount[sp]) {
-      const int buf = Sp->parity;
-      drain_one<F, MODE>(I, *Sp, sm, sp, buf, Sp->k, F::view(I, sp, buf), I.queue[sp][e]);
-    }
+    const int64_t e = (tile - first) * BLOCK + t;
+    if (e < qn) drain_one<F, MODE>(I, *Sp, sm, sp, buf, k, F::view(I, sp, buf), gload_rec(I.queue[sp] + e));
   }
   if (seg >= 0) flush_counters<BLOCK>(sm, Sp, seg & 1);
 }
@@ -1293,7 +1325,7 @@ k_init(const InstDev *__restrict__ insts, InstState *__restrict__ states, int in
   int cell = 0;
   float off = 0.0f;
   if constexpr (F::prec == 1) to_state32(I, x, cell, off);
-  write_new<F>(I, P, i, x, cell, off, vx, vy, vz, id, kn);
+  write_new<F>(I, P, i, x, cell, off, vx, vy, vz, id, kn, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1315,7 +1347,7 @@ k_diag(const InstDev *__restrict__ insts, const InstState *__restrict__ states, 
          i += (int64_t)gridDim.x * blockDim.x) {
       double vx, vy, vz;
       if constexpr (F::prec == 1) {
-        if (P.cell[i] < 0) continue;
+        if (!hw_live(P.hw[i])) continue;
         vx = P.vx[i]; vy = P.cold[i].vy; vz = P.cold[i].vz;
       } else {
         if (!(P.x[i] >= 0.0)) continue;
@@ -1416,7 +1448,7 @@ k_moments(const InstDev *__restrict__ insts, const InstState *__restrict__ state
       N = I.N;
       gather = I.gather;
       G = grid_par(I);
-      ext = S.extent[seg & 1];
+      ext = uni((int64_t)S.extent[seg & 1]);
       P = F::view(I, seg & 1, S.parity);
       const int ne = (gather == 0) ? N : ((gather == 1) ? N + 1 : N + 2);
       for (int j = t; j < ne; j += BLOCK) sE[j] = I.E64[j];
@@ -1433,8 +1465,9 @@ k_moments(const InstDev *__restrict__ insts, const InstState *__restrict__ state
       double xi = 0.0, vx = 0.0;
       if (ok) {
         if constexpr (F::prec == 1) {
-          j = P.cell[i];
-          ok = j >= 0;
+          const uint32_t w = P.hw[i];
+          j = hw_cell(w);
+          ok = hw_live(w);
           if (ok) {
             xi = (double)P.off[i];
             vx = (double)P.vx[i];
@@ -1508,6 +1541,34 @@ k_moments(const InstDev *__restrict__ insts, const InstState *__restrict__ state
   if (seg >= 0) flush();
 }
 
+// The FP32 hot words of instance inst re-expressed from step k1 after its
+// step index changed from k0 (pic_set_step): the countdowns count from the
+// step, the candidacies they stand for stay where they are.
+__global__ void __launch_bounds__(256)
+k_reencode(const InstDev *__restrict__ insts, const InstState *__restrict__ states, int inst,
+           int64_t k0, int64_t k1) {
+  CInst &I = cinst(insts)[inst];
+  const InstState &S = states[inst];
+  for (int s = 0; s < I.nsp; ++s) {
+    const P32 P = view32(I.pbuf[s][S.parity], I.cap[s]);
+    const int64_t ext = S.extent[s];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ext;
+         i += (int64_t)gridDim.x * blockDim.x) {
+      const uint32_t w = P.hw[i];
+      if (!hw_live(w)) continue;
+      const int64_t kn = hw_knext(w, hw_far(w) ? P.knext[i] : 0, k0);
+      const uint32_t nw = hw_encode(hw_cell(w), kn, k1);
+      P.hw[i] = nw;
+      if (hw_far(nw)) P.knext[i] = (int32_t)kn;
+    }
+  }
+}
+
+void launch_reencode(const InstDev *insts, InstState *states, int inst, int64_t k0, int64_t k1,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_reencode, dim3(1024), dim3(256), 0, s, insts, states, inst, k0, k1);
+}
+
 __global__ void k_zero_deposit(const InstDev *__restrict__ insts, const InstState *__restrict__ states) {
   CInst &I = cinst(insts)[blockIdx.x];
   const InstState &S = states[blockIdx.x];
@@ -1527,7 +1588,7 @@ size_t particle_lds_bytes(int prec, int max_n, int block) {
   const size_t tables =
       (prec == 1) ? ((np1 * 8 + 15) & ~(size_t)15) + (size_t)max_n * 16 + (np1 + 1) * 4
                   : np1 * 24 + 8;
-  const size_t q = (size_t)(block / 64) * kWaveQ * sizeof(int);
+  const size_t q = (size_t)(block / 64) * kWaveQ * sizeof(int4);
   return ((tables + 15) & ~(size_t)15) + q;
 }
 

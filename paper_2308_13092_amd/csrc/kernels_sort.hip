@@ -29,8 +29,8 @@ struct SortSmem {
 
 __device__ __forceinline__ int key_of(CInst &I, const P32 &P, int64_t i, const double *,
                                       const double *) {
-  const int c = P.cell[i];
-  return (c >= 0 && c < I.N) ? c : -1;
+  const uint32_t w = P.hw[i];
+  return (hw_live(w) && hw_cell(w) < I.N) ? hw_cell(w) : -1;
 }
 __device__ __forceinline__ int key_of(CInst &I, const P64 &P, int64_t i, const double *nodes,
                                       const double *h) {
@@ -99,10 +99,10 @@ constexpr int kCTile = kSB * 16;   // particles per tile of the count kernel
 __device__ __forceinline__ void count_keys(CInst &I, const P32 &P, int64_t i0, int64_t ext,
                                            const double *, int *key) {
   if (i0 + 4 <= ext) {
-    const int4 c = gload4(P.cell + i0);
-    const int cc[4] = {c.x, c.y, c.z, c.w};
+    const int4 c = gload4(reinterpret_cast<const int *>(P.hw) + i0);
+    const uint32_t cc[4] = {(uint32_t)c.x, (uint32_t)c.y, (uint32_t)c.z, (uint32_t)c.w};
 #pragma unroll
-    for (int q = 0; q < 4; ++q) key[q] = (cc[q] >= 0 && cc[q] < I.N) ? cc[q] : -1;
+    for (int q = 0; q < 4; ++q) key[q] = (hw_live(cc[q]) && hw_cell(cc[q]) < I.N) ? hw_cell(cc[q]) : -1;
   } else {
 #pragma unroll
     for (int q = 0; q < 4; ++q) key[q] = (i0 + q < ext) ? key_of(I, P, i0 + q, nullptr, nullptr) : -1;
@@ -152,7 +152,7 @@ k_sort_count(const InstDev *__restrict__ insts, const InstState *__restrict__ st
       seg = s;
       Ip = &cinst(insts)[seg >> 1];
       const InstState &S = states[seg >> 1];
-      ext = S.extent[seg & 1];
+      ext = uni((int64_t)S.extent[seg & 1]);   // scalar: no wait on vector memory per tile
       view = make_view<P>(*Ip, seg & 1, S.parity);
       if (sizeof(P) == sizeof(P64) && !Ip->uniform)
         for (int j = threadIdx.x; j <= Ip->N; j += kSB) sNodes[j] = Ip->nodes[j];
@@ -212,7 +212,7 @@ k_sort_scan(const InstDev *__restrict__ insts, InstState *__restrict__ states) {
 
 // One particle's fields in registers.
 struct Rec32 {   // 4-byte fields only (the id as two words): kept in registers
-  int cell; float off, vx, vy, vz; int knext; uint32_t id_lo, id_hi;
+  uint32_t hw; float off, vx, vy, vz; int knext; uint32_t id_lo, id_hi;
 };
 struct Rec64 {
   double x, vx, vy, vz; int knext; uint64_t id;
@@ -225,10 +225,10 @@ template <> struct RecOf<P64> { using T = Rec64; };
 // all four are inside the extent).
 __device__ __forceinline__ void load_recs(const P32 &P, int64_t i0, int64_t ext, Rec32 *r, bool *ok) {
   if (i0 + 4 <= ext) {
-    const int4 c = gload4(P.cell + i0);
+    const int4 c = gload4(reinterpret_cast<const int *>(P.hw) + i0);
     const float4 o = gload4(P.off + i0), x = gload4(P.vx + i0);
     const int4 k = gload4(P.knext + i0);
-    const int cc[4] = {c.x, c.y, c.z, c.w};
+    const uint32_t cc[4] = {(uint32_t)c.x, (uint32_t)c.y, (uint32_t)c.z, (uint32_t)c.w};
     const float oo[4] = {o.x, o.y, o.z, o.w}, xx[4] = {x.x, x.y, x.z, x.w};
     const int kk[4] = {k.x, k.y, k.z, k.w};
 #pragma unroll
@@ -243,10 +243,10 @@ __device__ __forceinline__ void load_recs(const P32 &P, int64_t i0, int64_t ext,
     for (int q = 0; q < 4; ++q) {
       const int64_t i = i0 + q;
       ok[q] = i < ext;
-      r[q] = Rec32{-1, 0.0f, 0.0f, 0.0f, 0.0f, 0, 0u, 0u};
+      r[q] = Rec32{kHwDead, 0.0f, 0.0f, 0.0f, 0.0f, 0, 0u, 0u};
       if (ok[q]) {
         const ecpic_iv4 cd = *(const ECPIC_GLOBAL ecpic_iv4 *)(P.cold + i);
-        r[q] = Rec32{P.cell[i], P.off[i], P.vx[i], __int_as_float(cd.x), __int_as_float(cd.y),
+        r[q] = Rec32{P.hw[i], P.off[i], P.vx[i], __int_as_float(cd.x), __int_as_float(cd.y),
                      P.knext[i], (uint32_t)cd.z, (uint32_t)cd.w};
       }
     }
@@ -284,7 +284,7 @@ __device__ __forceinline__ void load_recs(const P64 &P, int64_t i0, int64_t ext,
 }
 
 __device__ __forceinline__ void store_rec(const P32 &P, int64_t d, const Rec32 &r) {
-  gstore<int>(P.cell + d, r.cell);
+  gstore<uint32_t>(P.hw + d, r.hw);
   gstore<float>(P.off + d, r.off);
   gstore<float>(P.vx + d, r.vx);
   gstore<int>(P.knext + d, r.knext);
@@ -300,7 +300,7 @@ __device__ __forceinline__ void store_rec(const P64 &P, int64_t d, const Rec64 &
   gstore<uint64_t>(P.id + d, r.id);
 }
 __device__ __forceinline__ int rec_key(CInst &I, const Rec32 &r, const double *) {
-  return (r.cell >= 0 && r.cell < I.N) ? r.cell : -1;
+  return (hw_live(r.hw) && hw_cell(r.hw) < I.N) ? hw_cell(r.hw) : -1;
 }
 __device__ __forceinline__ int rec_key(CInst &I, const Rec64 &r, const double *nodes) {
   const double x = r.x;
@@ -347,7 +347,7 @@ k_sort_scatter(const InstDev *__restrict__ insts, InstState *__restrict__ states
       seg = s;
       Ip = &cinst(insts)[seg >> 1];
       const InstState &S = states[seg >> 1];
-      ext = S.extent[seg & 1];
+      ext = uni((int64_t)S.extent[seg & 1]);   // scalar: no wait on vector memory per tile
       src = make_view<P>(*Ip, seg & 1, S.parity);
       dst = make_view<P>(*Ip, seg & 1, S.parity ^ 1);
       if (sizeof(P) == sizeof(P64) && !Ip->uniform)
