@@ -318,14 +318,25 @@ __device__ __forceinline__ int rec_key(CInst &I, const Rec64 &r, const double *n
   return lo;
 }
 
+// The scatter.  A workgroup takes its contiguous range of tiles piece by
+// piece (a piece: its tiles of one segment) in three phases:
+//   1. an LDS histogram of the piece's cells (keys only);
+//   2. one HBM atomic per nonzero cell reserves the piece's range of that
+//      cell's destination slots;
+//   3. every particle takes the next slot of its cell's range from an LDS
+//      cursor and is copied there.
+// Phase 3 has no barrier and no HBM atomic per tile, so its wavefronts stream
+// independently.  Lanes with equal keys (particles arrive nearly sorted) take
+// one cursor atomic per run and consecutive slots, so their stores coalesce.
+// Order within a cell is not defined.
 template <class P>
 __global__ void __launch_bounds__(kSB)
 k_sort_scatter(const InstDev *__restrict__ insts, InstState *__restrict__ states, int n_inst,
                int max_n) {
   __shared__ SortSmem sm;
   extern __shared__ __align__(16) unsigned char dsm[];
-  // LDS: per-cell counts u32, per-cell destination bases u64 and, FP64
-  // only, the node positions to locate x.
+  // LDS: per-cell counts / cursors u32, per-cell destination bases u64 and,
+  // FP64 only, the node positions to locate x.
   unsigned int *cnt = reinterpret_cast<unsigned int *>(dsm);
   unsigned long long *gbase = reinterpret_cast<unsigned long long *>(dsm + 4 * ((max_n + 2) & ~1));
   double *sNodes = reinterpret_cast<double *>(gbase + max_n);
@@ -334,64 +345,70 @@ k_sort_scatter(const InstDev *__restrict__ insts, InstState *__restrict__ states
   const int nseg = 2 * n_inst;
   const int64_t T = sm.seg_prefix[nseg];
   const int64_t t0 = T * blockIdx.x / gridDim.x, t1 = T * (blockIdx.x + 1) / gridDim.x;
-  int seg = -1;
-  CInst *Ip = nullptr;
-  P src, dst;
-  int64_t ext = 0;
-  for (int64_t tile = t0; tile < t1; ++tile) {
-    int s = seg < 0 ? segment_of(sm.seg_prefix, nseg, tile) : seg;
-    while (sm.seg_prefix[s + 1] <= tile) ++s;
-    s = __builtin_amdgcn_readfirstlane(s);
-    if (s != seg) {
-      __syncthreads();
-      seg = s;
-      Ip = &cinst(insts)[seg >> 1];
-      const InstState &S = states[seg >> 1];
-      ext = uni((int64_t)S.extent[seg & 1]);   // scalar: no wait on vector memory per tile
-      src = make_view<P>(*Ip, seg & 1, S.parity);
-      dst = make_view<P>(*Ip, seg & 1, S.parity ^ 1);
-      if (sizeof(P) == sizeof(P64) && !Ip->uniform)
-        for (int j = threadIdx.x; j <= Ip->N; j += kSB) sNodes[j] = Ip->nodes[j];
-      __syncthreads();
-    }
-    CInst &I = *Ip;
-    const int64_t i0 = (tile - sm.seg_prefix[seg]) * kSTile + (int64_t)threadIdx.x * kSPPT;
-    typename RecOf<P>::T r[kSPPT];
-    bool ok[kSPPT];
+  int64_t tile = t0;
+  while (tile < t1) {
+    // the piece [tile, pe) of segment seg
+    int seg = segment_of(sm.seg_prefix, nseg, tile);
+    while (sm.seg_prefix[seg + 1] <= tile) ++seg;
+    seg = uni(seg);
+    const int64_t first = uni((int64_t)sm.seg_prefix[seg]);
+    const int64_t pe = min(t1, uni((int64_t)sm.seg_prefix[seg + 1]));
+    CInst &I = cinst(insts)[seg >> 1];
+    const InstState &S = states[seg >> 1];
+    const int64_t ext = uni((int64_t)S.extent[seg & 1]);
+    const int par = uni(S.parity);
+    const P src = make_view<P>(I, seg & 1, par);
+    const P dst = make_view<P>(I, seg & 1, par ^ 1);
+    const int N = I.N;
+    if (sizeof(P) == sizeof(P64) && !I.uniform)
+      for (int j = threadIdx.x; j <= N; j += kSB) sNodes[j] = I.nodes[j];
+    __syncthreads();
+    // 1. histogram of the piece's keys
+    for (int64_t tt = tile; tt < pe; ++tt) {
+      const int64_t i0 = (tt - first) * kSTile + (int64_t)threadIdx.x * kSPPT;
 #pragma unroll
-    for (int g = 0; g < kSPPT; g += 4) load_recs(src, i0 + g, ext, r + g, ok + g);
-    int key[kSPPT];
-    unsigned int rank[kSPPT];
-    // Rank of each particle among the tile's particles of its cell: one LDS
-    // atomic per run of equal cells across the lanes (for a given q the
-    // lanes hold particles 4 apart, still in nearly sorted order; the order
-    // within a cell is not defined).
+      for (int g = 0; g < kSPPT; g += 4) {
+        int key[4];
+        count_keys(I, src, i0 + g, ext, sNodes, key);
 #pragma unroll
-    for (int q = 0; q < kSPPT; ++q) {
-      key[q] = ok[q] ? rec_key(I, r[q], sNodes) : -1;
-      int len, pos;
-      unsigned int b0 = 0;
-      if (key_run(key[q], len, pos) && key[q] >= 0) b0 = atomicAdd(&cnt[key[q]], (unsigned int)len);
-      b0 = __shfl(b0, __lane_id() - pos, 64);
-      rank[q] = b0 + (unsigned int)pos;
+        for (int q = 0; q < 4; ++q) {
+          int len, pos;
+          if (key_run(key[q], len, pos) && key[q] >= 0) atomicAdd(&cnt[key[q]], (unsigned int)len);
+        }
+      }
     }
     __syncthreads();
-    // The first particle of each cell in the tile reserves the tile's range.
-#pragma unroll
-    for (int q = 0; q < kSPPT; ++q)
-      if (key[q] >= 0 && rank[q] == 0)
-        gbase[key[q]] = atomicAdd(&I.scursor[seg & 1][key[q]], (unsigned long long)cnt[key[q]]);
+    // 2. reserve each cell's slots for the piece; the counts become cursors
+    for (int j = threadIdx.x; j < N; j += kSB) {
+      const unsigned int c = cnt[j];
+      if (c) {
+        gbase[j] = atomicAdd(&I.scursor[seg & 1][j], (unsigned long long)c);
+        cnt[j] = 0;
+      }
+    }
     __syncthreads();
-    // cnt was last read by the reservations above: clear it for the next
-    // tile here, so that the barrier below orders the clearing before the
-    // next tile's rank atomics in every wavefront.
+    // 3. copy every particle to the next slot of its cell
+    for (int64_t tt = tile; tt < pe; ++tt) {
+      const int64_t i0 = (tt - first) * kSTile + (int64_t)threadIdx.x * kSPPT;
+      typename RecOf<P>::T r[kSPPT];
+      bool ok[kSPPT];
 #pragma unroll
-    for (int q = 0; q < kSPPT; ++q)
-      if (key[q] >= 0 && rank[q] == 0) cnt[key[q]] = 0;
+      for (int g = 0; g < kSPPT; g += 4) load_recs(src, i0 + g, ext, r + g, ok + g);
 #pragma unroll
-    for (int q = 0; q < kSPPT; ++q)
-      if (key[q] >= 0) store_rec(dst, (int64_t)(gbase[key[q]] + rank[q]), r[q]);
+      for (int q = 0; q < kSPPT; ++q) {
+        const int key = ok[q] ? rec_key(I, r[q], sNodes) : -1;
+        int len, pos;
+        unsigned int b0 = 0;
+        if (key_run(key, len, pos) && key >= 0) b0 = atomicAdd(&cnt[key], (unsigned int)len);
+        b0 = __shfl(b0, __lane_id() - pos, 64);
+        if (key >= 0) store_rec(dst, (int64_t)(gbase[key] + b0 + (unsigned int)pos), r[q]);
+      }
+    }
     __syncthreads();
+    // the cursors of the piece's cells back to zero for the next piece
+    for (int j = threadIdx.x; j < N; j += kSB) cnt[j] = 0;
+    __syncthreads();
+    tile = pe;
   }
 }
 
