@@ -304,6 +304,21 @@ pic_status pic_moments(pic_ctx *ctx, int32_t inst, int32_t species, double *ux, 
 pic_status pic_impacts(pic_ctx *ctx, int32_t inst, int32_t species, int32_t wall, int64_t *energy,
                        int64_t *angle);
 
+/* Checkpoint and resume of one instance.  A checkpoint holds everything a
+ * run needs to continue bit for bit: the step index, status and cumulative
+ * counters, the averaged profile, EEDF, moment and impact accumulators, and
+ * the particle arrays as stored (the deposit of x^k is rebuilt exactly by the
+ * next step).  pic_checkpoint_bytes gives the size for the current state;
+ * pic_checkpoint_save writes it to a host buffer of at least that size
+ * (PIC_EINVAL if smaller; synchronises); pic_checkpoint_load restores it into
+ * slot inst of any context whose configuration of that slot is the same (grid,
+ * drive, gas, weight, time step, capacity, averaging, seed, state form;
+ * PIC_EINVAL if not, with the slot unchanged).  The buffer is the caller's;
+ * its layout is this library version's own. */
+pic_status pic_checkpoint_bytes(pic_ctx *ctx, int32_t inst, size_t *bytes);
+pic_status pic_checkpoint_save(pic_ctx *ctx, int32_t inst, void *buf, size_t bytes);
+pic_status pic_checkpoint_load(pic_ctx *ctx, int32_t inst, const void *buf, size_t bytes);
+
 /* Re-initialise slot inst with cfg (n_cells == 0 empties it), taking memory
  * from the arena pool.  PIC_ENOMEM when the pool cannot hold it. */
 pic_status pic_slot_reset(pic_ctx *ctx, int32_t inst, const pic_config *cfg);

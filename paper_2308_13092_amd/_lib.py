@@ -97,6 +97,9 @@ SIGNATURES = [
     ("pic_profiles", C.c_int, [_CTX, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     ("pic_impacts", C.c_int, [_CTX, C.c_int32, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
     ("pic_moments", C.c_int, [_CTX, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    ("pic_checkpoint_bytes", C.c_int, [_CTX, C.c_int32, C.POINTER(C.c_size_t)]),
+    ("pic_checkpoint_save", C.c_int, [_CTX, C.c_int32, C.c_void_p, C.c_size_t]),
+    ("pic_checkpoint_load", C.c_int, [_CTX, C.c_int32, C.c_void_p, C.c_size_t]),
     ("pic_slot_reset", C.c_int, [_CTX, C.c_int32, C.POINTER(pic_config)]),
     ("pic_slot_release", C.c_int, [_CTX, C.c_int32]),
     ("pic_slot_bytes", C.c_size_t, [C.POINTER(pic_config)]),
@@ -392,6 +395,22 @@ class Context:
         st = self.lib.pic_impacts(self.ctx, inst, species, wall, _ptr(out["energy"]), _ptr(out["angle"]))
         self._check(st, "pic_impacts", allow=(PIC_ECAPACITY, PIC_ENONFINITE, PIC_EGROWTH))
         return out
+
+    # -- checkpoint and resume -------------------------------------------------
+    def checkpoint(self, inst):
+        """The instance's restorable state as bytes (pic_checkpoint_save)."""
+        n = C.c_size_t()
+        self._check(self.lib.pic_checkpoint_bytes(self.ctx, inst, C.byref(n)), "pic_checkpoint_bytes")
+        buf = np.empty(n.value, dtype=np.uint8)
+        st = self.lib.pic_checkpoint_save(self.ctx, inst, C.c_void_p(buf.ctypes.data), n.value)
+        self._check(st, "pic_checkpoint_save", allow=(PIC_ECAPACITY, PIC_ENONFINITE, PIC_EGROWTH))
+        return buf.tobytes()
+
+    def restore(self, inst, data):
+        """Load a checkpoint into slot ``inst`` (pic_checkpoint_load)."""
+        buf = np.frombuffer(data, dtype=np.uint8)
+        self._check(self.lib.pic_checkpoint_load(self.ctx, inst, C.c_void_p(buf.ctypes.data), len(buf)),
+                    "pic_checkpoint_load")
 
     # -- slots, tuning, timing ------------------------------------------------
     def slot_reset(self, inst, cfg):

@@ -1249,6 +1249,176 @@ pic_status pic_impacts(pic_ctx *c, int32_t inst, int32_t species, int32_t wall, 
   return status_of(S.status);
 }
 
+// ---------------------------------------------------------------------------
+// Checkpoint and resume of one instance
+// ---------------------------------------------------------------------------
+namespace {
+// What a checkpoint must agree on with the slot it is loaded into: the
+// configuration that fixes the layout, the grid and the arithmetic.
+struct CkptCfg {
+  int32_t N, bc, gather, prec, nsp, collisions, avg_every, eedf_every, eedf_bins, imp_bins, imp_abins,
+      moments;
+  int64_t cap[2], avg_start, k_stop;
+  double L, W, dt, v_rf, w_rf, phase, n_g, t_gas, vt_see, gamma_see, nu_max[2], growth_limit,
+      eedf_de, eedf_half, imp_escale;
+  uint64_t seed;
+};
+struct CkptHeader {
+  char magic[8];
+  uint32_t version, prec;
+  int64_t extent[2];
+  uint64_t total;
+  CkptCfg cfg;
+};
+constexpr uint32_t kCkptVersion = 1;
+const char kCkptMagic[8] = {'E', 'C', 'P', 'I', 'C', 'C', 'K', '1'};
+
+CkptCfg ckpt_cfg(const pic_ctx *c, int inst) {
+  CkptCfg k;
+  std::memset(&k, 0, sizeof k);
+  const InstDev &I = c->host_inst[inst];
+  const pic_config &g = c->slots[inst].cfg;
+  k.N = I.N; k.bc = I.bc; k.gather = I.gather; k.prec = c->prec; k.nsp = I.nsp;
+  k.collisions = I.collisions; k.avg_every = I.avg_every; k.eedf_every = I.eedf_every;
+  k.eedf_bins = I.eedf_bins; k.imp_bins = I.imp_bins; k.imp_abins = I.imp_abins; k.moments = I.moments;
+  k.cap[0] = I.cap[0]; k.cap[1] = I.cap[1]; k.avg_start = I.avg_start; k.k_stop = I.k_stop;
+  k.L = I.L; k.W = I.W; k.dt = I.dt; k.v_rf = I.v_rf; k.w_rf = I.w_rf; k.phase = I.phase; k.n_g = I.n_g;
+  k.t_gas = g.t_gas_k; k.vt_see = I.vt_see; k.gamma_see = I.gamma_see; k.nu_max[0] = I.nu_max[0];
+  k.nu_max[1] = I.nu_max[1]; k.growth_limit = I.growth_limit; k.eedf_de = I.eedf_de;
+  k.eedf_half = I.eedf_half; k.imp_escale = I.imp_escale; k.seed = I.seed;
+  return k;
+}
+
+// The device arrays of a checkpoint, in order: (pointer, bytes).
+std::vector<std::pair<char *, size_t>> ckpt_arrays(const pic_ctx *c, int inst, const int64_t ext[2],
+                                                   int parity) {
+  const InstDev &I = c->host_inst[inst];
+  const size_t n1 = (size_t)I.N + 1, N = (size_t)I.N;
+  std::vector<std::pair<char *, size_t>> a;
+  auto add = [&](void *p, size_t b) { a.emplace_back((char *)p, b); };
+  add(I.accA[0], 8 * n1);
+  add(I.accA[1], 8 * n1);
+  add(I.acc_phi, 8 * n1);
+  for (int s = 0; s < 2; ++s) {
+    add(I.accM1[s], 8 * n1);
+    add(I.accM2[s], 8 * n1);
+    add(I.accP[s], 8 * N);
+  }
+  add(I.eedf, 8 * (size_t)I.eedf_bins);
+  add(I.impact, 8 * 4 * ((size_t)I.imp_bins + 1 + (size_t)I.imp_abins));
+  for (int s = 0; s < I.nsp; ++s) {
+    const size_t e = (size_t)ext[s];
+    char *b = I.pbuf[s][parity];
+    if (c->prec == PIC_FP32_STATE) {
+      const P32 P = view32(b, I.cap[s]);
+      add(P.hw, 4 * e);
+      add(P.off, 4 * e);
+      add(P.vx, 4 * e);
+      add(P.knext, 4 * e);
+      add(P.cold, sizeof(Cold32) * e);
+    } else {
+      const P64 P = view64(b, I.cap[s]);
+      add(P.x, 8 * e);
+      add(P.vx, 8 * e);
+      add(P.vy, 8 * e);
+      add(P.vz, 8 * e);
+      add(P.knext, 4 * e);
+      add(P.id, 8 * e);
+    }
+  }
+  return a;
+}
+
+size_t ckpt_total(const std::vector<std::pair<char *, size_t>> &a, size_t n_nodes) {
+  size_t t = sizeof(CkptHeader) + sizeof(InstState) + 8 * n_nodes;
+  for (auto &x : a) t += x.second;
+  return t;
+}
+}  // namespace
+
+pic_status pic_checkpoint_bytes(pic_ctx *c, int32_t inst, size_t *bytes) {
+  pic_status r = check_inst(c, inst);
+  if (r != PIC_OK) return r;
+  if (!bytes) return fail(c, PIC_EINVAL, "null output");
+  InstState S;
+  r = read_state(c, inst, S);
+  if (r != PIC_OK) return r;
+  *bytes = ckpt_total(ckpt_arrays(c, inst, S.extent, S.parity), c->slots[inst].nodes.size());
+  return PIC_OK;
+}
+
+pic_status pic_checkpoint_save(pic_ctx *c, int32_t inst, void *buf, size_t bytes) {
+  pic_status r = check_inst(c, inst);
+  if (r != PIC_OK) return r;
+  if (!buf) return fail(c, PIC_EINVAL, "null buffer");
+  InstState S;
+  r = read_state(c, inst, S);
+  if (r != PIC_OK) return r;
+  const auto arrays = ckpt_arrays(c, inst, S.extent, S.parity);
+  const std::vector<double> &nodes = c->slots[inst].nodes;
+  const size_t total = ckpt_total(arrays, nodes.size());
+  if (bytes < total) return fail(c, PIC_EINVAL, "checkpoint buffer smaller than pic_checkpoint_bytes");
+  char *o = (char *)buf;
+  CkptHeader h;
+  std::memset(&h, 0, sizeof h);
+  std::memcpy(h.magic, kCkptMagic, 8);
+  h.version = kCkptVersion;
+  h.prec = (uint32_t)c->prec;
+  h.extent[0] = S.extent[0];
+  h.extent[1] = S.extent[1];
+  h.total = total;
+  h.cfg = ckpt_cfg(c, inst);
+  std::memcpy(o, &h, sizeof h);
+  o += sizeof h;
+  std::memcpy(o, &S, sizeof S);
+  o += sizeof S;
+  std::memcpy(o, nodes.data(), 8 * nodes.size());
+  o += 8 * nodes.size();
+  for (auto &a : arrays) {
+    if (a.second) HIP_TRY(c, hipMemcpy(o, a.first, a.second, hipMemcpyDeviceToHost));
+    o += a.second;
+  }
+  return status_of(S.status);
+}
+
+pic_status pic_checkpoint_load(pic_ctx *c, int32_t inst, const void *buf, size_t bytes) {
+  pic_status r = check_inst(c, inst);
+  if (r != PIC_OK) return r;
+  if (!buf || bytes < sizeof(CkptHeader) + sizeof(InstState)) return fail(c, PIC_EINVAL, "checkpoint too short");
+  const char *o = (const char *)buf;
+  CkptHeader h;
+  std::memcpy(&h, o, sizeof h);
+  o += sizeof h;
+  if (std::memcmp(h.magic, kCkptMagic, 8) != 0 || h.version != kCkptVersion)
+    return fail(c, PIC_EINVAL, "not a checkpoint of this library version");
+  const CkptCfg mine = ckpt_cfg(c, inst);
+  if (h.prec != (uint32_t)c->prec || std::memcmp(&h.cfg, &mine, sizeof mine) != 0)
+    return fail(c, PIC_EINVAL, "checkpoint configuration differs from the slot's");
+  const InstDev &I = c->host_inst[inst];
+  for (int s = 0; s < 2; ++s)
+    if (h.extent[s] < 0 || h.extent[s] > I.cap[s]) return fail(c, PIC_EINVAL, "checkpoint extent beyond capacity");
+  const std::vector<double> &nodes = c->slots[inst].nodes;
+  InstState S;
+  std::memcpy(&S, o, sizeof S);
+  o += sizeof S;
+  if (std::memcmp(o, nodes.data(), 8 * nodes.size()) != 0)
+    return fail(c, PIC_EINVAL, "checkpoint grid differs from the slot's");
+  o += 8 * nodes.size();
+  if (S.extent[0] != h.extent[0] || S.extent[1] != h.extent[1] || (S.parity != 0 && S.parity != 1))
+    return fail(c, PIC_EINVAL, "corrupt checkpoint state");
+  const auto arrays = ckpt_arrays(c, inst, S.extent, S.parity);
+  const size_t total = ckpt_total(arrays, nodes.size());
+  if (h.total != total || bytes < total) return fail(c, PIC_EINVAL, "checkpoint size mismatch");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (auto &a : arrays) {
+    if (a.second) HIP_TRY(c, hipMemcpy(a.first, o, a.second, hipMemcpyHostToDevice));
+    o += a.second;
+  }
+  HIP_TRY(c, hipMemcpy(c->d_state + inst, &S, sizeof S, hipMemcpyHostToDevice));
+  c->deposit_current = false;   // the next step rebuilds the deposit of x^k (exact)
+  return PIC_OK;
+}
+
 pic_status pic_slot_reset(pic_ctx *c, int32_t inst, const pic_config *cfg) {
   if (!c || !cfg) return PIC_EINVAL;
   if (inst < 0 || inst >= c->n_inst) return fail(c, PIC_EINVAL, "instance index out of range");
