@@ -55,6 +55,7 @@ INT32_MAX = 2 ** 31 - 1
 TWO_PI = 2.0 * math.pi
 
 BC_DIRICHLET, BC_PERIODIC = 0, 1
+WC_UNIT = 4          # weight class of weight W (classes 0-7: W 2^(c-4))
 GATHER_EC, GATHER_MC, GATHER_EC2 = 0, 1, 2
 FP64, FP32 = 0, 1
 
@@ -228,10 +229,17 @@ class Species:
     x: np.ndarray = None      # FP64 form
     cell: np.ndarray = None   # FP32 form
     off: np.ndarray = None
+    wc: np.ndarray = None     # weight class c (uint8): weight W 2^(c-4); None = all 4
 
     @property
     def n(self):
         return int(self.id.shape[0])
+
+    def classes(self):
+        """Weight class of every particle (4, weight W, unless set)."""
+        if self.wc is None:
+            return np.full(self.n, WC_UNIT, dtype=np.uint8)
+        return self.wc
 
     def subset(self, m):
         kw = dict(s=self.s, prec=self.prec, vx=self.vx[m], vy=self.vy[m], vz=self.vz[m],
@@ -241,6 +249,8 @@ class Species:
         else:
             kw["cell"] = self.cell[m]
             kw["off"] = self.off[m]
+        if self.wc is not None:
+            kw["wc"] = self.wc[m]
         return Species(**kw)
 
     def append(self, other: "Species"):
@@ -249,6 +259,8 @@ class Species:
         kw = dict(s=self.s, prec=self.prec)
         for f in ("vx", "vy", "vz", "id", "knext") + (("x",) if self.prec == FP64 else ("cell", "off")):
             kw[f] = np.concatenate([getattr(self, f), getattr(other, f)])
+        if self.wc is not None or other.wc is not None:
+            kw["wc"] = np.concatenate([self.classes(), other.classes()])
         return Species(**kw)
 
     def order_by_id(self):
@@ -301,9 +313,16 @@ def fold_s2(grid: Grid, m):
     return m
 
 
-def deposit_species(grid: Grid, sp: Species, gather=GATHER_EC):
+def weight_shift(sp: Species, u):
+    """Per particle, the power of two of its weight in the deposit's unit
+    W 2^-u: c - 4 + u (0 for every particle without rebalancing, u = 0)."""
+    return sp.classes().astype(np.int64) - WC_UNIT + int(u)
+
+
+def deposit_species(grid: Grid, sp: Species, gather=GATHER_EC, u=0):
     """A_{s,n} = sum over particles of the weights of node n (int64, exact):
-    S1 for EC and MC, S2 for second-order EC."""
+    S1 for EC and MC, S2 for second-order EC; a particle of weight class c
+    adds its weights times 2^(c - 4 + u), in units of W 2^-u 2^-32."""
     A = np.zeros(grid.N + 1, dtype=np.int64)
     if sp.n == 0:
         return A
@@ -312,15 +331,16 @@ def deposit_species(grid: Grid, sp: Species, gather=GATHER_EC):
     else:
         j = sp.cell.astype(np.int64)
         xi = sp.off.astype(np.float64)
+    sh = weight_shift(sp, u)
     if gather == GATHER_EC2:
         n, wl, wc, wr = weights_s2(j, xi)
-        np.add.at(A, fold_s2(grid, n - 1), wl)
-        np.add.at(A, n, wc)
-        np.add.at(A, fold_s2(grid, n + 1), wr)
+        np.add.at(A, fold_s2(grid, n - 1), wl << sh)
+        np.add.at(A, n, wc << sh)
+        np.add.at(A, fold_s2(grid, n + 1), wr << sh)
     else:
         w0, w1 = weights(xi)
-        np.add.at(A, j, w0)
-        np.add.at(A, j + 1, w1)
+        np.add.at(A, j, w0 << sh)
+        np.add.at(A, j + 1, w1 << sh)
     if grid.bc == BC_PERIODIC:
         A[0] += A[grid.N]
         A[grid.N] = A[0]
@@ -568,7 +588,8 @@ def push_fp32(grid: Grid, sp: Species, E32, gather, qmdt32, tables):
 # ---------------------------------------------------------------------------
 # Secondary electron emission at the electrodes (not in the paper)
 # ---------------------------------------------------------------------------
-def emit_secondaries(grid: Grid, ion_ids, walls, k, seed, gamma, t_see_ev, dt, prec, nudt_e):
+def emit_secondaries(grid: Grid, ion_ids, walls, k, seed, gamma, t_see_ev, dt, prec, nudt_e,
+                     ion_wc=None):
     """Each absorbed ion emits one electron at its wall with probability gamma.
 
     |vx| = v_t sqrt(-2 ln u) (flux-weighted half Maxwellian), vy, vz Maxwellian,
@@ -594,6 +615,8 @@ def emit_secondaries(grid: Grid, ion_ids, walls, k, seed, gamma, t_see_ev, dt, p
     ids = ids_from_words(p1[ok], p2[ok])
     sp = Species(s=0, prec=prec, vx=vx[ok], vy=vt * zy[ok], vz=vt * zz[ok], id=ids,
                  knext=next_candidate(ids, k, 0, seed, nudt_e))
+    if ion_wc is not None:
+        sp.wc = np.asarray(ion_wc)[ok]     # the electron carries the ion's weight
     if prec == FP64:
         sp.x = x[ok]
     else:

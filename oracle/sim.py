@@ -24,7 +24,7 @@ from .pic import (BC_PERIODIC, FP64, GATHER_EC, GATHER_EC2, TAG_CHILD, TWO_M32, 
                   Species, collide_electrons, collide_ions, deposit_species, draw, emit_secondaries,
                   field_ec, field_ec2, field_mc, fold_s2, gas_velocity, gather_fp32, gather_fp64,
                   ids_from_words, init_species, locate, next_candidate, node_charge, poisson,
-                  push_fp32, push_fp64, s2_gather_index)
+                  push_fp32, push_fp64, s2_gather_index, weight_shift)
 
 DEFAULTS = dict(
     n_cells=128, bc=0, nodes=None, gap_m=0.025, v_rf=200.0, f_rf=13.56e6, phase=0.0,
@@ -33,7 +33,7 @@ DEFAULTS = dict(
     gamma_see=0.0, t_see_ev=2.0, seed=1, n_species=2, collisions=1, pullback=0,
     nu_max_e=0.0, nu_max_i=0.0, avg_start=0, avg_every=0, eedf_every=0, eedf_bins=200,
     eedf_emax_ev=50.0, eedf_width_m=1e-3, impact_bins=0, impact_angle_bins=0, impact_emax_ev=0.0,
-    moments=0,
+    moments=0, rebalance_ppc=0, rebalance_dv_e=0.0, rebalance_dv_i=0.0,
 )
 
 
@@ -77,6 +77,10 @@ class Sim:
         if W == 0.0:
             W = c["n0_m3"] * g.L / c["n_per_species"]
         self.W = W
+        # With rebalancing, weights are W 2^(c-4) for classes c = 0..7 and
+        # deposits and weighted sums are kept in units of W 2^-4.
+        self.u = 4 if int(c["rebalance_ppc"]) > 0 else 0
+        self.W_unit = W * 2.0 ** -self.u
         self.n_g = ph.gas_density(c["p_pa"], c["t_gas_k"])
         nu_e = float(c["nu_max_e"]) or ph.nu_max_electron(self.n_g)
         nu_i = float(c["nu_max_i"]) or ph.nu_max_ion(self.n_g, c["v_rf"], c["t_gas_k"])
@@ -86,7 +90,7 @@ class Sim:
         self.q = [ph.SPECIES[s][0] for s in range(2)]
         self.m = [ph.SPECIES[s][1] for s in range(2)]
         self.qmdt = [(self.q[s] / self.m[s]) * self.dt for s in range(2)]
-        self.qW = [self.q[s] * W for s in range(2)]
+        self.qW = [self.q[s] * self.W_unit for s in range(2)]
         self.vti = math.sqrt(ph.KB * c["t_gas_k"] / ph.M_AR)
         self.seed = int(c["seed"])
         if self.prec != FP64:
@@ -132,7 +136,7 @@ class Sim:
 
     # -- steps 1-3 --------------------------------------------------------
     def deposit(self):
-        self.A = [deposit_species(self.grid, sp, self.gather) for sp in self.sp]
+        self.A = [deposit_species(self.grid, sp, self.gather, self.u) for sp in self.sp]
         return self.A
 
     def solve(self):
@@ -190,6 +194,7 @@ class Sim:
             j = sp.cell.astype(np.int64)
             xi = sp.off.astype(np.float64)
         vx = sp.vx.astype(np.float64)
+        f = np.ldexp(1.0, weight_shift(sp, self.u))     # the particle's weight in units W 2^-u
         E = self.E
         if self.gather == GATHER_EC2:
             up = xi >= 0.5
@@ -200,18 +205,18 @@ class Sim:
             wr = 0.5 * (b * b)
             wc = 1.0 - wl - wr
             for idx, w in ((fold_s2(self.grid, n - 1), wl), (n, wc), (fold_s2(self.grid, n + 1), wr)):
-                np.add.at(self.acc_m1[s], idx, w * vx)
-                np.add.at(self.acc_m2[s], idx, w * (vx * vx))
+                np.add.at(self.acc_m1[s], idx, (f * w) * vx)
+                np.add.at(self.acc_m2[s], idx, (f * w) * (vx * vx))
             m, t = s2_gather_index(j, xi)
             e = (1.0 - t) * E[m] + t * E[m + 1]
         else:
             w0, w1 = 1.0 - xi, xi
-            np.add.at(self.acc_m1[s], j, w0 * vx)
-            np.add.at(self.acc_m1[s], j + 1, w1 * vx)
-            np.add.at(self.acc_m2[s], j, w0 * (vx * vx))
-            np.add.at(self.acc_m2[s], j + 1, w1 * (vx * vx))
+            np.add.at(self.acc_m1[s], j, (f * w0) * vx)
+            np.add.at(self.acc_m1[s], j + 1, (f * w1) * vx)
+            np.add.at(self.acc_m2[s], j, (f * w0) * (vx * vx))
+            np.add.at(self.acc_m2[s], j + 1, (f * w1) * (vx * vx))
             e = E[j] if self.gather == GATHER_EC else (1.0 - xi) * E[j] + xi * E[j + 1]
-        np.add.at(self.acc_p[s], j, vx * e)
+        np.add.at(self.acc_p[s], j, f * (vx * e))
 
     def moments(self, s):
         """Mean x-velocity (m/s) and x-temperature (eV) at the nodes, power
@@ -239,7 +244,9 @@ class Sim:
         k = self.k
         return c["eedf_every"] > 0 and k >= c["avg_start"] and (k - c["avg_start"]) % c["eedf_every"] == 0
 
-    def _sample_eedf(self, x, vx, vy, vz):
+    def _sample_eedf(self, x, vx, vy, vz, sh):
+        """Central EEDF sample; a particle counts its weight in units W 2^-u
+        (2^sh; 1 without rebalancing)."""
         c = self.cfg
         centre = 0.5 * self.L
         half = 0.5 * c["eedf_width_m"]
@@ -248,8 +255,8 @@ class Sim:
         eps = ph.HALF_ME_OVER_QE * v2
         de = c["eedf_emax_ev"] / c["eedf_bins"]
         b = np.floor(eps / de)
-        b = b[b < c["eedf_bins"]].astype(np.int64)
-        np.add.at(self.eedf, b, 1)
+        keep = b < c["eedf_bins"]
+        np.add.at(self.eedf, b[keep].astype(np.int64), np.int64(1) << sh[m][keep])
         self.eedf_samples += 1
 
     # -- one full step ------------------------------------------------------
@@ -270,13 +277,14 @@ class Sim:
             if self.prec == FP64:
                 vx, x, wall = push_fp64(g, sp, self.E, self.gather, self.qmdt[s], self.dt)
                 moved = Species(s=s, prec=FP64, vx=vx, vy=sp.vy, vz=sp.vz, id=sp.id,
-                                knext=sp.knext, x=x)
+                                knext=sp.knext, x=x, wc=sp.wc)
             else:
                 vx, cell, off, wall = push_fp32(g, sp, self.E32, self.gather, self.qmdt32[s],
                                                 self.tables)
                 moved = Species(s=s, prec=sp.prec, vx=vx, vy=sp.vy, vz=sp.vz, id=sp.id,
-                                knext=sp.knext, cell=cell, off=off)
+                                knext=sp.knext, cell=cell, off=off, wc=sp.wc)
             gone = wall != 0
+            sh = weight_shift(moved, self.u)
             if gone.any():
                 for wi, wv in ((0, -1), (1, 1)):
                     mw = wall == wv
@@ -286,17 +294,21 @@ class Sim:
                     vza = moved.vz[mw].astype(np.float64)
                     v2 = (vxa * vxa + vya * vya) + vza * vza
                     en = (0.5 * self.m[s] / ph.QE) * v2
-                    self.absorbed_energy_ev[s, wi] += float(np.sum(en))
+                    # energies and histogram counts carry the particle's weight
+                    # (units W 2^-u)
+                    fw = np.ldexp(1.0, sh[mw])
+                    self.absorbed_energy_ev[s, wi] += float(np.sum(fw * en))
                     if len(en):
                         self.last_absorbed.append((s, wi, en, vxa, v2))
                     if c["avg_every"] > 0 and k >= c["avg_start"] and len(en):
                         be, ba = impact_bins(en, vxa, v2, self.imp_nb, self.imp_na, self.imp_emax)
-                        np.add.at(self.impact_e[s, wi], be, 1)
-                        np.add.at(self.impact_a[s, wi], ba, 1)
+                        np.add.at(self.impact_e[s, wi], be, np.int64(1) << sh[mw])
+                        np.add.at(self.impact_a[s, wi], ba, np.int64(1) << sh[mw])
                 if s == 1 and self.nsp > 1:
                     see_new = emit_secondaries(g, moved.id[gone], wall[gone], k, self.seed,
                                                c["gamma_see"], c["t_see_ev"], self.dt, self.prec,
-                                               self.nudt[0])
+                                               self.nudt[0],
+                                               ion_wc=None if moved.wc is None else moved.wc[gone])
                     if see_new is not None:
                         self.see_emitted += see_new.n
             live = moved.subset(~gone)
@@ -306,7 +318,7 @@ class Sim:
                 else:
                     xs = g.position(live.cell, live.off)
                 self._sample_eedf(xs, live.vx.astype(np.float64), live.vy.astype(np.float64),
-                                  live.vz.astype(np.float64))
+                                  live.vz.astype(np.float64), weight_shift(live, self.u))
             survivors.append(live)
 
         new_e, new_i = [], []
@@ -338,6 +350,8 @@ class Sim:
                         pos["cell"] = sp.cell[ci][iz]
                         pos["off"] = sp.off[ci][iz]
                     cast = (lambda a: a) if self.prec == FP64 else (lambda a: a.astype(np.float32))
+                    if sp.wc is not None:     # the pair carries the primary's weight
+                        pos["wc"] = sp.wc[ci][iz]
                     new_e.append(Species(s=0, prec=self.prec, vx=cast(ej[0]), vy=cast(ej[1]),
                                          vz=cast(ej[2]), id=eid,
                                          knext=next_candidate(eid, k, 0, self.seed, self.nudt[0]),
@@ -373,12 +387,13 @@ class Sim:
 
     # -- diagnostics ----------------------------------------------------------
     def kinetic_energy(self, s):
-        """W sum_i (m/2) |v_i|^2 per unit area (J/m^2)."""
+        """sum_i W_i (m/2) |v_i|^2 per unit area (J/m^2), W_i the particle's weight."""
         sp = self.sp[s]
         vx = sp.vx.astype(np.float64)
         vy = sp.vy.astype(np.float64)
         vz = sp.vz.astype(np.float64)
-        return self.W * (0.5 * self.m[s]) * float(np.sum((vx * vx + vy * vy) + vz * vz))
+        f = np.ldexp(1.0, weight_shift(sp, self.u))
+        return self.W_unit * (0.5 * self.m[s]) * float(np.sum(f * ((vx * vx + vy * vy) + vz * vz)))
 
     def monitors(self):
         """The three stability conditions of Section 1 (Eqs 1a-1c), in the
@@ -398,7 +413,7 @@ class Sim:
         """
         g = self.grid
         A_e = np.asarray(self.A[0], dtype=np.float64)
-        ne = ((A_e * self.W) * TWO_M32) / g.V
+        ne = ((A_e * self.W_unit) * TWO_M32) / g.V
         ne_max = float(ne.max())
         wpe = math.sqrt(ne_max * ph.QE * ph.QE / (ph.EPS0 * ph.ME))
         sp = self.sp[0]
@@ -407,12 +422,20 @@ class Sim:
         vx = sp.vx.astype(np.float64)
         vy = sp.vy.astype(np.float64)
         vz = sp.vz.astype(np.float64)
-        mean_ev = float(np.mean(ph.HALF_ME_OVER_QE * ((vx * vx + vy * vy) + vz * vz))) if sp.n else 0.0
+        f = np.ldexp(1.0, weight_shift(sp, self.u))      # weighted mean over the electrons
+        mean_ev = float(np.sum(f * (ph.HALF_ME_OVER_QE * ((vx * vx + vy * vy) + vz * vz))) / np.sum(f)) \
+            if sp.n else 0.0
         te = 2.0 * mean_ev / 3.0
         lde = math.sqrt(ph.EPS0 * te / (ne_max * ph.QE)) if ne_max > 0 else 0.0
         return dict(ne_max_m3=ne_max, wpe_dt_max=wpe * self.dt,
                     vmax_dt_over_dxmin=vmax * self.dt / hmin, lambda_de_over_dxmin=lde / hmin,
                     te_ev=te)
+
+    def rebalance(self):
+        """Merge and split particles toward rebalance_ppc per cell (Section 3d;
+        see oracle/rebalance.py); returns [(merges, splits) per species]."""
+        from .rebalance import rebalance
+        return rebalance(self)
 
     def positions(self, s):
         sp = self.sp[s]
@@ -423,7 +446,7 @@ class Sim:
     def profiles(self):
         """RF-averaged electron and ion densities (m^-3), potential (V), EEDF counts."""
         n = max(self.n_samples, 1)
-        scale = self.W * TWO_M32
+        scale = self.W_unit * TWO_M32
         dens = [(self.acc_A[s] * scale) / (self.grid.V * n) for s in range(2)]
         return dict(ne=dens[0], ni=dens[1], phi=self.acc_phi / n, eedf=self.eedf.copy(),
                     n_samples=self.n_samples, eedf_samples=self.eedf_samples)
