@@ -92,6 +92,46 @@ def run_gpu(cfg, steps, warmup, autotune=False):
     return out
 
 
+def run_rebalanced(n_per_species, steps, warmup, every=1000, settle=3):
+    """The large discharge with particle rebalancing: a few passes at the start
+    bring the cell counts near the target (the narrowest cells' initial
+    count), then the run rebalances every ``every`` steps inside the timed
+    window as well."""
+    import torch
+    from paper_2308_13092_amd import Context, configs
+    cfg = configs.large_rebalanced(n_per_species=n_per_species, every=every)
+    ctx = Context([cfg])
+    live0 = int(sum(ctx.diagnostics()["n_live"]))
+    pass_ms = []
+    for _ in range(settle):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.rebalance()
+        torch.cuda.synchronize()
+        pass_ms.append(1e3 * (time.perf_counter() - t0))
+    live1 = int(sum(ctx.diagnostics()["n_live"]))
+    ctx.step(warmup)
+    torch.cuda.synchronize()
+    d0 = ctx.diagnostics()
+    t0 = time.perf_counter()
+    ctx.step(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    d1 = ctx.diagnostics()
+    ps = int(d1["particle_steps"] - d0["particle_steps"])
+    out = dict(value=ps / el, unit="particle-steps/s", ms_per_step=1e3 * el / steps, steps=steps,
+               target_ppc=int(cfg["rebalance_ppc"]), every=every,
+               passes_in_window=(int(d0["step"]) + steps) // every - int(d0["step"]) // every,
+               live_initial=live0, live_after_settling=live1, live_end=int(sum(d1["n_live"])),
+               pass_ms=[round(v, 2) for v in pass_ms],
+               merges=[int(v) for v in d1["merges"]], splits=[int(v) for v in d1["splits"]],
+               status=int(d1["status"]))
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_sweep(steps, warmup, n_inst=256):
     """Workload 4: the batched sweep of independent discharges, all advanced by
     the same graph-replayed steps."""
@@ -244,6 +284,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-rebalance", action="store_true")
     ap.add_argument("--sweep-steps", type=int, default=2000)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=16,
@@ -304,6 +345,14 @@ def main():
                                   sort_ms_per_launch=round(kt64["sort_ms"] / max(kt64["sort_launches"], 1), 4)))
         print(f"[bench] fp64: {r64['value']:.4g} p-s/s, kernel {avg64:.4f} ms", file=sys.stderr, flush=True)
 
+    rebal = None
+    if not a.no_rebalance:
+        rebal = run_rebalanced(a.particles, a.steps, a.warmup)
+        rebal["step_speedup_vs_off"] = round(r32["ms_per_step"] / rebal["ms_per_step"], 3)
+        print(f"[bench] rebalanced: {rebal['ms_per_step']:.3f} ms/step ({rebal['step_speedup_vs_off']}x "
+              f"faster per step), live {rebal['live_initial']} -> {rebal['live_end']}, "
+              f"passes {rebal['pass_ms']} ms", file=sys.stderr, flush=True)
+
     sweep = None
     if not a.no_sweep:
         sweep = run_sweep(a.sweep_steps, 100)
@@ -347,6 +396,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fp64_plain": fp64,
+        "rebalanced": rebal,
         "batched_sweep": sweep,
         "serving": serving,
         "small_workloads": small,

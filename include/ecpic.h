@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define PIC_ABI_VERSION 5
+#define PIC_ABI_VERSION 6
 
 typedef struct pic_ctx pic_ctx;  /* opaque; owns host-side metadata only */
 
@@ -119,6 +119,16 @@ typedef struct pic_config {
      averaged steps (an extra pass over the particles on each of them);
      0: off. */
   int32_t moments;
+  /* Particle rebalancing toward rebalance_ppc particles per cell and species
+     (Section 3d: with it the fewer cells of a refined grid mean fewer
+     particles).  0 = off.  FP32 state form only.  A rebalanced discharge's
+     particles carry weights W 2^(w-4), w = 0..7 (4 at the start), and its
+     deposit and weighted sums are in units of W/16.  See pic_rebalance. */
+  int32_t rebalance_ppc;
+  int32_t rebalance_every;  /* pic_step rebalances every this many steps (context-wide:
+                               the value of the first active instance); 0 = never  */
+  double rebalance_dv_e;    /* velocity-bin width of merges (m/s); 0 -> sqrt(e te / m_e) / 4 */
+  double rebalance_dv_i;    /* the same for ions; 0 -> sqrt(e ti / M) / 4                 */
 } pic_config;
 
 #define PIC_MAX_CELLS 2048
@@ -152,6 +162,8 @@ typedef struct pic_diag {
   double lambda_de_over_dxmin;   /* sqrt(eps0 T / (n_e,max e)) / min h, T = 2<KE>/3 (1a) */
   double nu_max[2];              /* null-collision bounds in use [electrons, ions] (1/s):
                                     the configured values, or those the library computed */
+  int64_t merges[2];             /* rebalancing: quadruples merged into pairs           */
+  int64_t splits[2];             /* rebalancing: particles split in two                 */
 } pic_diag;
 
 #define PIC_ST_CAPACITY 1
@@ -170,6 +182,7 @@ typedef struct pic_state_view {
   void *vx, *vy, *vz; /* velocity components (double* or float*)                    */
   uint64_t *id;     /* particle id (Philox key)                                      */
   int32_t *knext;   /* first step at which the particle is a collision candidate     */
+  uint8_t *wclass;  /* FP32: weight class w (weight W 2^(w-4)); NULL on set = all 4  */
 } pic_state_view;
 
 /* Launch tuning (chosen by the autotuner, or set by hand). */
@@ -240,6 +253,19 @@ pic_status pic_step(pic_ctx *ctx, int32_t n_steps);
 
 /* Sort the particles of every active discharge by cell and drop absorbed ones. */
 pic_status pic_sort(pic_ctx *ctx);
+
+/* One particle-rebalancing pass over every discharge with rebalance_ppc > 0
+ * (Section 3d names rebalancing, without an algorithm; this one is exact in
+ * charge): per species, a cell with more than 2P particles (P = rebalance_ppc)
+ * merges, within each group of its particles of equal weight class w < 7 and
+ * velocity bin floor(vx / dv) taken in id order, every full quadruple into two
+ * particles of class w + 1 at the quadruple's mean offset with velocities
+ * v_mean +- delta e (weight exact, momentum and kinetic energy to rounding);
+ * a cell with fewer than P/2 splits every particle of class w > 0 into two of
+ * class w - 1.  Between steps; the particles end cell-sorted and the next step
+ * rebuilds the deposit.  Synchronises.  PIC_ENOMEM if the slot's scratch is
+ * too small, PIC_ECAPACITY if splits overflow a capacity. */
+pic_status pic_rebalance(pic_ctx *ctx);
 
 /* Counters and monitors of one instance (synchronises). */
 pic_status pic_diagnostics(pic_ctx *ctx, int32_t inst, pic_diag *out);

@@ -34,7 +34,8 @@ class pic_config(C.Structure):
         ("eedf_every", C.c_int32), ("eedf_bins", C.c_int32), ("eedf_emax_ev", C.c_double),
         ("eedf_width_m", C.c_double), ("k_stop", C.c_int64), ("growth_limit", C.c_double),
         ("impact_bins", C.c_int32), ("impact_angle_bins", C.c_int32), ("impact_emax_ev", C.c_double),
-        ("moments", C.c_int32),
+        ("moments", C.c_int32), ("rebalance_ppc", C.c_int32), ("rebalance_every", C.c_int32),
+        ("rebalance_dv_e", C.c_double), ("rebalance_dv_i", C.c_double),
     ]
 
 
@@ -50,6 +51,7 @@ class pic_diag(C.Structure):
         ("bound_violations", C.c_int64), ("particle_steps", C.c_int64), ("ne_max_m3", C.c_double),
         ("wpe_dt_max", C.c_double), ("vmax_dt_over_dxmin", C.c_double),
         ("lambda_de_over_dxmin", C.c_double), ("nu_max", C.c_double * 2),
+        ("merges", C.c_int64 * 2), ("splits", C.c_int64 * 2),
     ]
 
 
@@ -58,6 +60,7 @@ class pic_state_view(C.Structure):
         ("n", C.c_int64), ("x", C.POINTER(C.c_double)), ("cell", C.POINTER(C.c_int32)),
         ("off", C.POINTER(C.c_float)), ("vx", C.c_void_p), ("vy", C.c_void_p), ("vz", C.c_void_p),
         ("id", C.POINTER(C.c_uint64)), ("knext", C.POINTER(C.c_int32)),
+        ("wclass", C.POINTER(C.c_uint8)),
     ]
 
 
@@ -87,6 +90,7 @@ SIGNATURES = [
     ("pic_mcc", C.c_int, [_CTX]),
     ("pic_step", C.c_int, [_CTX, C.c_int32]),
     ("pic_sort", C.c_int, [_CTX]),
+    ("pic_rebalance", C.c_int, [_CTX]),
     ("pic_diagnostics", C.c_int, [_CTX, C.c_int32, C.POINTER(pic_diag)]),
     ("pic_diagnostics_noalloc", C.c_int, [_CTX, C.POINTER(C.c_int32), C.c_int32, C.POINTER(pic_diag)]),
     ("pic_get_state", C.c_int, [_CTX, C.c_int32, C.c_int32, C.POINTER(pic_state_view)]),
@@ -258,6 +262,9 @@ class Context:
     def sort(self):
         self._check(self.lib.pic_sort(self.ctx), "pic_sort")
 
+    def rebalance(self):
+        self._check(self.lib.pic_rebalance(self.ctx), "pic_rebalance")
+
     # -- results --------------------------------------------------------------
     def diagnostics(self, inst=0, allow_error=False):
         d = pic_diag()
@@ -321,6 +328,9 @@ class Context:
         out["knext"] = np.empty(n, np.int32)
         v.id = out["id"].ctypes.data_as(C.POINTER(C.c_uint64))
         v.knext = out["knext"].ctypes.data_as(C.POINTER(C.c_int32))
+        if self.prec == 1:
+            out["wc"] = np.empty(n, np.uint8)
+            v.wclass = out["wc"].ctypes.data_as(C.POINTER(C.c_uint8))
         st = self.lib.pic_get_state(self.ctx, inst, species, C.byref(v))
         self._check(st, "pic_get_state", allow=(PIC_ECAPACITY, PIC_ENONFINITE, PIC_EGROWTH))
         m = int(v.n)
@@ -347,6 +357,9 @@ class Context:
         keep["knext"] = np.ascontiguousarray(np.minimum(st["knext"], 2 ** 31 - 1), np.int32)
         v.id = keep["id"].ctypes.data_as(C.POINTER(C.c_uint64))
         v.knext = keep["knext"].ctypes.data_as(C.POINTER(C.c_int32))
+        if self.prec == 1 and st.get("wc") is not None:
+            keep["wc"] = np.ascontiguousarray(st["wc"], np.uint8)
+            v.wclass = keep["wc"].ctypes.data_as(C.POINTER(C.c_uint8))
         self._check(self.lib.pic_set_state(self.ctx, inst, species, C.byref(v)), "pic_set_state")
 
     def set_step(self, inst, k):

@@ -14,7 +14,7 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libecpic.so")
-SOURCES = ["kernels_field.hip", "kernels_particles.hip", "kernels_sort.hip", "noalloc.hip", "api.cpp"]
+SOURCES = ["kernels_field.hip", "kernels_particles.hip", "kernels_sort.hip", "kernels_rebalance.hip", "noalloc.hip", "api.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

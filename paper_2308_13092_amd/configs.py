@@ -83,6 +83,16 @@ def large(n_per_species=32_000_000, precision=1, seed=3, **over):
 LARGE_STEPS = 5000
 
 
+def large_rebalanced(n_per_species=32_000_000, precision=1, seed=3, every=1000, **over):
+    """Workload 3 with particle rebalancing (Section 3d): the target count per
+    cell is the initial count of the narrowest cells (n_per_species / 4912),
+    so the sheath keeps its particles per cell while the 8x wider centre cells
+    are merged toward the same count; a pass runs every ``every`` steps."""
+    ppc = max(1, int(round(n_per_species / 4912.0)))
+    return large(n_per_species=n_per_species, precision=precision, seed=seed, rebalance_ppc=ppc,
+                 rebalance_every=every, **over)
+
+
 def sweep(n=256, master_seed=13092, precision=1, scale=1.0):
     """Workload 4: n independent discharges drawn from a master seed."""
     g = np.random.Generator(np.random.PCG64(master_seed))

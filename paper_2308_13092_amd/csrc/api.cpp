@@ -80,13 +80,15 @@ struct SlotHost {
   size_t off = 0, bytes = 0;
   pic_config cfg{};
   std::vector<double> nodes;
+  RbScratch rb;                 // rebalancing scratch (rebalanced slots only)
 };
 
 // Grid block layout (offsets relative to the slot block).
 struct GridLayout {
   size_t nodes, h, V, dtoh, rf, rb, runs, A[2][2], phi, E64, E32, accA[2], acc_phi, accM1[2], accM2[2],
       accP[2], eedf, impact, scount[2],
-      scursor[2], queue[2], particles, total;
+      scursor[2], queue[2], rb_flag[2], rb_words, rb_k64[2], rb_k32[2], rb_val[2], rb_temp, rb_temp_bytes,
+      rb_items, particles, total;
 };
 
 int eff_bins(const pic_config &c) { return c.eedf_bins > 0 ? c.eedf_bins : 200; }
@@ -99,6 +101,10 @@ int64_t eff_cap(const pic_config &c) {
   return (cap + 63) / 64 * 64;
 }
 int bytes_per_particle(int prec) { return prec == PIC_FP32_STATE ? (int)kBytes32 : (int)kBytes64; }
+
+// Scratch reserved for the rebalancing radix sorts of `items` entries (the
+// size the sorts ask for is checked against it when the slot is set up).
+size_t rb_temp_reserve(size_t items) { return ((size_t)64 << 20) + 8 * items; }
 
 GridLayout layout(const pic_config &c) {
   GridLayout g{};
@@ -131,6 +137,18 @@ GridLayout layout(const pic_config &c) {
   for (int s = 0; s < 2; ++s) g.scursor[s] = take(8 * n1);
   // queue records of 16 B, at most one per particle and pass
   for (int s = 0; s < 2; ++s) g.queue[s] = take((s == 0 || c.n_species != 1) ? 16 * (size_t)eff_cap(c) : 0);
+  // rebalancing: per-cell flags, the candidate list (both species) and the
+  // radix sorts' scratch
+  const bool rb = c.rebalance_ppc > 0;
+  const size_t items = rb ? (size_t)(c.n_species == 1 ? 1 : 2) * (size_t)eff_cap(c) : 0;
+  g.rb_items = items;
+  for (int s = 0; s < 2; ++s) g.rb_flag[s] = take(rb ? N : 0);
+  g.rb_words = take(rb ? 64 : 0);
+  for (int b = 0; b < 2; ++b) g.rb_k64[b] = take(8 * items);
+  for (int b = 0; b < 2; ++b) g.rb_k32[b] = take(4 * items);
+  for (int b = 0; b < 2; ++b) g.rb_val[b] = take(4 * items);
+  g.rb_temp_bytes = rb ? rb_temp_reserve(items) : 0;
+  g.rb_temp = take(g.rb_temp_bytes);
   g.particles = o;
   const int nsp = c.n_species == 1 ? 1 : 2;
   o += (size_t)nsp * 2 * align_up((size_t)eff_cap(c) * bytes_per_particle(c.precision));
@@ -181,6 +199,9 @@ std::string validate(const pic_config &c) {
   if (c.nu_max_e < 0.0 || c.nu_max_i < 0.0) return "nu_max must be >= 0";
   if (!std::isfinite(c.v_rf) || !std::isfinite(c.f_rf) || !std::isfinite(c.phase))
     return "RF drive must be finite";
+  if (c.rebalance_ppc < 0 || c.rebalance_every < 0) return "negative rebalancing parameter";
+  if (c.rebalance_ppc > 0 && c.precision != PIC_FP32_STATE) return "rebalancing needs the FP32 state form";
+  if (!(c.rebalance_dv_e >= 0.0) || !(c.rebalance_dv_i >= 0.0)) return "rebalance_dv must be >= 0";
   return "";
 }
 
@@ -237,6 +258,7 @@ struct pic_ctx {
   // launches: on every workload measured they beat graph replay (by about
   // 10 % on the small and resolved discharges, 1 % on the large one).
   pic_tuning tune{1024, 0, 0, 0};
+  int rebalance_every = 0;     // pic_step rebalances every this many steps (0 = never)
   int64_t host_step = 0;
   bool deposit_current = false;
   std::string err;
@@ -415,7 +437,15 @@ static pic_status setup_slot(pic_ctx *c, int i, const pic_config &cfg) {
   I.gamma_see = cfg.gamma_see;
   double W = cfg.weight_m2;
   if (W == 0.0 && cfg.n_per_species > 0) W = cfg.n0_m3 * L / (double)cfg.n_per_species;
-  I.W = W;
+  // A rebalanced discharge keeps its deposit in units of W/16 (weights W 2^(w-4)).
+  I.wunit = cfg.rebalance_ppc > 0 ? 4 : 0;
+  I.W = std::ldexp(W, -I.wunit);
+  I.rb_ppc = cfg.rebalance_ppc;
+  {
+    const double te[2] = {cfg.te_ev, cfg.ti_ev}, ms[2] = {kME, kMAR}, dvg[2] = {cfg.rebalance_dv_e, cfg.rebalance_dv_i};
+    for (int s = 0; s < 2; ++s)
+      I.rb_dv[s] = dvg[s] > 0.0 ? dvg[s] : 0.25 * std::sqrt(std::max(te[s], 1e-6) * kQE / ms[s]);
+  }
   const double q[2] = {-kQE, kQE}, m[2] = {kME, kMAR};
   const double nu_e = cfg.nu_max_e > 0.0 ? cfg.nu_max_e : nu_max_electron_h(I.n_g);
   const double nu_i = cfg.nu_max_i > 0.0 ? cfg.nu_max_i : nu_max_ion_h(I.n_g, cfg.v_rf, cfg.t_gas_k);
@@ -427,7 +457,7 @@ static pic_status setup_slot(pic_ctx *c, int i, const pic_config &cfg) {
     I.qmdt32[s] = (float)I.qmdt[s];
     I.hq[s] = 0.5 * I.qmdt[s];
     I.hq32[s] = (float)I.hq[s];
-    I.qW[s] = q[s] * W;
+    I.qW[s] = q[s] * I.W;     // per deposit unit
     I.mass[s] = m[s];
   }
   I.int_path = (cfg.bc == PIC_BC_DIRICHLET_RF) && (I.nsp == 1 || I.qW[0] == -I.qW[1]);
@@ -468,6 +498,27 @@ static pic_status setup_slot(pic_ctx *c, int i, const pic_config &cfg) {
     I.scount[s] = (unsigned long long *)(base + g.scount[s]);
     I.scursor[s] = (unsigned long long *)(base + g.scursor[s]);
     I.queue[s] = (int4 *)(base + g.queue[s]);
+    I.rb_flag[s] = cfg.rebalance_ppc > 0 ? (unsigned char *)(base + g.rb_flag[s]) : nullptr;
+  }
+  sl.rb = RbScratch();
+  if (cfg.rebalance_ppc > 0) {
+    RbScratch &r = sl.rb;
+    r.words = (unsigned long long *)(base + g.rb_words);
+    for (int b = 0; b < 2; ++b) {
+      r.k64[b] = (unsigned long long *)(base + g.rb_k64[b]);
+      r.k32[b] = (uint32_t *)(base + g.rb_k32[b]);
+      r.val[b] = (uint32_t *)(base + g.rb_val[b]);
+    }
+    r.temp = base + g.rb_temp;
+    r.temp_bytes = g.rb_temp_bytes;
+    r.items = (int64_t)g.rb_items;
+    const size_t need = rb_sort_temp_bytes(r.items);
+    if (need == 0 || need > r.temp_bytes) {
+      c->pool.release(off, g.total);
+      sl = SlotHost();
+      return fail(c, PIC_ENOMEM, "rebalancing sort scratch: " + std::to_string(need) + " bytes asked, " +
+                                     std::to_string(g.rb_temp_bytes) + " reserved");
+    }
   }
   const size_t pb = align_up((size_t)cap * bytes_per_particle(cfg.precision));
   for (int s = 0; s < I.nsp; ++s)
@@ -697,13 +748,18 @@ static void fill_diag(const pic_ctx *c, int inst, const InstState &S, const unsi
   double vmax;
   std::memcpy(&vmax, &w[D_VMAX], 8);
   out->vmax_dt_over_dxmin = vmax * I.dt / I.hmin;
-  const double n_e = (double)out->n_live[0];
-  const double mean_ev = n_e > 0 ? ((double)w[D_KE0] * 0x1p-20) / n_e : 0.0;
+  // the electrons' mean energy, weighted (their summed weight in deposit units)
+  const double w_e = (double)w[D_WE];
+  const double mean_ev = w_e > 0 ? ((double)w[D_KE0] * 0x1p-20) / w_e : 0.0;
   const double te = 2.0 * mean_ev / 3.0;
   // lambda_De = sqrt(eps0 T_e / (n_e e)) with T_e in volts.
   out->lambda_de_over_dxmin = S.ne_max > 0 ? std::sqrt(kEPS0 * te / (S.ne_max * kQE)) / I.hmin : 0.0;
   out->nu_max[0] = I.nu_max[0];
   out->nu_max[1] = I.nu_max[1];
+  for (int s = 0; s < 2; ++s) {
+    out->merges[s] = (int64_t)S.ctr[C_MERGE][s];
+    out->splits[s] = (int64_t)S.ctr[C_SPLIT][s];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -788,6 +844,11 @@ pic_status pic_init(const pic_config *cfgs, int32_t n_inst, void *device_arena, 
   for (int i = 0; i < n_inst; ++i)
     if (cfgs[i].n_cells > 0 && cfgs[i].sort_interval > 0) {
       c->tune.sort_interval = cfgs[i].sort_interval;
+      break;
+    }
+  for (int i = 0; i < n_inst; ++i)
+    if (cfgs[i].n_cells > 0 && cfgs[i].rebalance_ppc > 0 && cfgs[i].rebalance_every > 0) {
+      c->rebalance_every = cfgs[i].rebalance_every;
       break;
     }
   // Static region.
@@ -890,6 +951,37 @@ pic_status pic_sort(pic_ctx *c) {
   return PIC_OK;
 }
 
+pic_status pic_rebalance(pic_ctx *c) {
+  if (!c) return PIC_EINVAL;
+  bool any = false;
+  for (int i = 0; i < c->n_inst; ++i) any |= c->slots[i].used && c->host_inst[i].rb_ppc > 0;
+  if (!any) return PIC_OK;
+  // cell order (and the cell ranges the flags are read from)
+  HIP_TRY(c, launch_sort(c->d_inst, c->d_state, c->n_inst, c->prec, sort_grid(c), c->max_n, c->stream));
+  for (int i = 0; i < c->n_inst; ++i) {
+    if (!c->slots[i].used || c->host_inst[i].rb_ppc <= 0) continue;
+    InstState S;
+    pic_status r = read_state(c, i, S);
+    if (r != PIC_OK) return r;
+    if (S.frozen) continue;
+    const hipError_t e = launch_rebalance(c->d_inst, c->d_state, i, c->host_inst[i].N, c->slots[i].rb, c->stream);
+    if (e == hipErrorInvalidValue) return fail(c, PIC_ENOMEM, "rebalancing list beyond its scratch");
+    if (e != hipSuccess) return fail(c, PIC_EDEVICE, std::string("rebalance: ") + hipGetErrorString(e));
+  }
+  // compact: the merged-away particles leave, the split children join the order
+  HIP_TRY(c, launch_sort(c->d_inst, c->d_state, c->n_inst, c->prec, sort_grid(c), c->max_n, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->deposit_current = false;
+  for (int i = 0; i < c->n_inst; ++i) {
+    if (!c->slots[i].used || c->host_inst[i].rb_ppc <= 0) continue;
+    InstState S;
+    pic_status r = read_state(c, i, S);
+    if (r != PIC_OK) return r;
+    if (S.status != 0) return status_of(S.status);
+  }
+  return PIC_OK;
+}
+
 pic_status pic_step(pic_ctx *c, int32_t n_steps) {
   if (!c || n_steps < 0) return PIC_EINVAL;
   bool any = false;
@@ -904,10 +996,12 @@ pic_status pic_step(pic_ctx *c, int32_t n_steps) {
   // by a sort) is closed by the next step's field launch: one launch fewer
   // per step.  Every call returns with its last step closed.
   bool open = false;
+  const int R = c->rebalance_every;
   for (int n = 0; n < n_steps; ++n) {
     const bool sort = S > 0 && ((c->host_step + 1) % S) == 0;
+    const bool rebal = R > 0 && ((c->host_step + 1) % R) == 0;
     if (c->timing || !c->tune.use_graph) {
-      const bool leave_open = !sort && n + 1 < n_steps;
+      const bool leave_open = !sort && !rebal && n + 1 < n_steps;
       pic_status r = enqueue_step(c, c->stream, sort, c->timing, open, leave_open);
       if (r != PIC_OK) return r;
       open = leave_open;
@@ -918,6 +1012,12 @@ pic_status pic_step(pic_ctx *c, int32_t n_steps) {
       HIP_TRY(c, hipGraphLaunch(g, c->stream));
     }
     c->host_step++;
+    if (rebal) {
+      pic_status r = pic_rebalance(c);
+      if (r != PIC_OK) return r;
+      r = pic_deposit(c);
+      if (r != PIC_OK) return r;
+    }
   }
   return PIC_OK;
 }
@@ -1027,6 +1127,7 @@ pic_status pic_get_state(pic_ctx *c, int32_t inst, int32_t species, pic_state_vi
     int64_t o = 0;
     for (int64_t i = 0; i < ext; ++i) {
       if (cell[i] < 0) continue;
+      if (v->wclass) v->wclass[o] = (uint8_t)hw_class(hw[i]);
       if (v->cell) v->cell[o] = cell[i];
       if (v->off) v->off[o] = off[i];
       if (v->vx) ((float *)v->vx)[o] = vx[i];
@@ -1075,6 +1176,10 @@ pic_status pic_set_state(pic_ctx *c, int32_t inst, int32_t species, const pic_st
     if (!v->cell || !v->off) return fail(c, PIC_EINVAL, "null cell/off");
     for (int64_t i = 0; i < n; ++i) {
       const float o = v->off[i];
+      const int w = v->wclass ? (int)v->wclass[i] : kClassUnit;
+      if (w > 7 || (I.wunit == 0 && w != kClassUnit))
+        return fail(c, PIC_EINVAL, "weight class of particle " + std::to_string(i) +
+                                       " out of range (only 4 without rebalancing)");
       if (v->cell[i] < 0 || v->cell[i] >= I.N || !(o >= 0.0f && o < 1.0f) ||
           !std::isfinite(((float *)v->vx)[i]) || !std::isfinite(((float *)v->vy)[i]) ||
           !std::isfinite(((float *)v->vz)[i]) || v->knext[i] < 0)
@@ -1098,7 +1203,8 @@ pic_status pic_set_state(pic_ctx *c, int32_t inst, int32_t species, const pic_st
     if (c->prec == PIC_FP32_STATE) {
       P32 P = view32(b, cap);
       std::vector<uint32_t> hw(n);
-      for (int64_t i = 0; i < n; ++i) hw[i] = hw_encode(v->cell[i], v->knext[i], S.k);
+      for (int64_t i = 0; i < n; ++i)
+        hw[i] = hw_encode(v->cell[i], v->knext[i], S.k, v->wclass ? (int)v->wclass[i] : kClassUnit);
       HIP_TRY(c, hipMemcpy(P.hw, hw.data(), 4 * n, hipMemcpyHostToDevice));
       HIP_TRY(c, hipMemcpy(P.off, v->off, 4 * n, hipMemcpyHostToDevice));
       HIP_TRY(c, hipMemcpy(P.vx, v->vx, 4 * n, hipMemcpyHostToDevice));
@@ -1257,10 +1363,10 @@ namespace {
 // configuration that fixes the layout, the grid and the arithmetic.
 struct CkptCfg {
   int32_t N, bc, gather, prec, nsp, collisions, avg_every, eedf_every, eedf_bins, imp_bins, imp_abins,
-      moments;
+      moments, wunit, rb_ppc;
   int64_t cap[2], avg_start, k_stop;
   double L, W, dt, v_rf, w_rf, phase, n_g, t_gas, vt_see, gamma_see, nu_max[2], growth_limit,
-      eedf_de, eedf_half, imp_escale;
+      eedf_de, eedf_half, imp_escale, rb_dv[2];
   uint64_t seed;
 };
 struct CkptHeader {
@@ -1286,6 +1392,7 @@ CkptCfg ckpt_cfg(const pic_ctx *c, int inst) {
   k.t_gas = g.t_gas_k; k.vt_see = I.vt_see; k.gamma_see = I.gamma_see; k.nu_max[0] = I.nu_max[0];
   k.nu_max[1] = I.nu_max[1]; k.growth_limit = I.growth_limit; k.eedf_de = I.eedf_de;
   k.eedf_half = I.eedf_half; k.imp_escale = I.imp_escale; k.seed = I.seed;
+  k.wunit = I.wunit; k.rb_ppc = I.rb_ppc; k.rb_dv[0] = I.rb_dv[0]; k.rb_dv[1] = I.rb_dv[1];
   return k;
 }
 

@@ -55,7 +55,7 @@ enum : int {
   C_PSTEPS = 0, C_ABS = 1,            // C_ABS + 2*species + wall (wall 0 left, 1 right)
   C_EABS = 5,                         // absorbed energy, 2^-16 eV units, same indexing
   C_SEE = 9, C_IZ = 10, C_EX = 11, C_EL = 12, C_CX = 13, C_CAND = 14,   // C_CAND + species
-  C_BOUND = 16, C_NONFINITE = 17
+  C_BOUND = 16, C_NONFINITE = 17, C_MERGE = 18, C_SPLIT = 19
 };
 
 enum : int { ST_CAPACITY = 1, ST_NONFINITE = 2, ST_GROWTH = 4 };
@@ -71,7 +71,10 @@ struct InstDev {
   double v_rf, w_rf, phase, growth_limit;
   double n_g, vti, vt_see, gamma_see;
   double nu_max[2], nudt[2], qmdt[2], qW[2], hq[2], mass[2];
-  double W, cgauss;
+  double W, cgauss;            // W: the unit weight of the deposit (class 4 weight x 2^-wunit)
+  int32_t wunit, rb_ppc;       // wunit: 4 for a rebalanced discharge, else 0; rb_ppc: target per cell
+  double rb_dv[2];             // velocity bin widths of the rebalancing merges (m/s)
+  unsigned char *rb_flag[2];   // per cell: 1 merge, 2 split (rebalancing pass)
   double eedf_de, eedf_centre, eedf_half, pad1;
   float qmdt32[2], hq32[2];
   float dtoh32u, pad2[3];
@@ -132,8 +135,10 @@ struct InstState {
 // The FP32 form's hot word
 // ---------------------------------------------------------------------------
 // bits 0-11  cell (0xFFF: dead slot; grids have at most 2048 cells)
-// bits 12-30 countdown c: steps from the current step k to the particle's next
+// bits 12-27 countdown c: steps from the current step k to the particle's next
 //            collision candidacy, knext = k + c
+// bits 28-30 weight class w: the particle's weight is W 2^(w-4) (4 unless
+//            the discharge is rebalanced)
 // bit  31    far: knext lies beyond the countdown's range (or before k); the
 //            knext array then holds it and c counts down towards a re-check
 // A candidate is a particle with c = 0 at its step (after a re-check of the
@@ -142,18 +147,23 @@ struct InstState {
 constexpr uint32_t kHwDead = 0xFFFFFFFFu;
 constexpr uint32_t kHwCell = 0xFFFu;
 constexpr int kHwShift = 12;
-constexpr uint32_t kCntMax = (1u << 19) - 1u;
+constexpr uint32_t kCntMax = (1u << 16) - 1u;
+constexpr int kHwClassShift = 28;
+constexpr uint32_t kHwClass = 7u << kHwClassShift;
 constexpr uint32_t kHwFar = 1u << 31;
+constexpr int kClassUnit = 4;   // the class of weight W
 __host__ __device__ inline int hw_cell(uint32_t w) { return (int)(w & kHwCell); }
 __host__ __device__ inline bool hw_live(uint32_t w) { return (w & kHwCell) != kHwCell; }
 __host__ __device__ inline uint32_t hw_cnt(uint32_t w) { return (w >> kHwShift) & kCntMax; }
 __host__ __device__ inline bool hw_far(uint32_t w) { return (w & kHwFar) != 0u; }
-// The hot word of a particle in `cell` whose next candidacy is step knext,
-// seen from step k.
-__host__ __device__ inline uint32_t hw_encode(int cell, int64_t knext, int64_t k) {
+__host__ __device__ inline int hw_class(uint32_t w) { return (int)((w >> kHwClassShift) & 7u); }
+// The hot word of a particle of weight class cls in `cell` whose next
+// candidacy is step knext, seen from step k.
+__host__ __device__ inline uint32_t hw_encode(int cell, int64_t knext, int64_t k, int cls) {
+  const uint32_t base = (uint32_t)cell | ((uint32_t)cls << kHwClassShift);
   const int64_t w = knext - k;
-  if (w >= 0 && w <= (int64_t)kCntMax) return (uint32_t)cell | ((uint32_t)w << kHwShift);
-  return (uint32_t)cell | ((w < 0 ? 0u : kCntMax) << kHwShift) | kHwFar;
+  if (w >= 0 && w <= (int64_t)kCntMax) return base | ((uint32_t)w << kHwShift);
+  return base | ((w < 0 ? 0u : kCntMax) << kHwShift) | kHwFar;
 }
 // The particle's next candidacy (far_knext: its entry of the knext array).
 __host__ __device__ inline int64_t hw_knext(uint32_t w, int32_t far_knext, int64_t k) {

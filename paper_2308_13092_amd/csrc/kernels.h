@@ -50,10 +50,30 @@ void launch_moments(const InstDev *insts, InstState *states, int n_inst, int pre
                     hipStream_t s);
 
 // Diagnostics reduction output layout (unsigned long long words): k_diag
-// writes the live counts, kinetic-energy sums and the electrons' max |vx|;
+// writes the live counts, kinetic-energy sums, the electrons' max |vx| and
+// summed weight;
 // k_deposit_total the two deposit totals.
 enum : int { D_LIVE0 = 0, D_LIVE1 = 1, D_KE0 = 2, D_KE1 = 3, D_VMAX = 4, D_DEP0 = 5, D_DEP1 = 6,
-             D_NWORDS = 8 };
+             D_WE = 7, D_NWORDS = 8 };   // D_WE: the electrons' summed weight (deposit units)
+
+// Rebalancing scratch of one slot (inside the slot's block): the candidate
+// list's keys and values, double-buffered for the radix sorts, their scratch,
+// and four counters.
+struct RbScratch {
+  unsigned long long *words = nullptr;   // [0] listed candidates, [2 + s] split children
+  unsigned long long *k64[2] = {nullptr, nullptr};
+  uint32_t *k32[2] = {nullptr, nullptr};
+  uint32_t *val[2] = {nullptr, nullptr};
+  void *temp = nullptr;
+  size_t temp_bytes = 0;
+  int64_t items = 0;                     // list capacity (both species' capacities)
+};
+// Scratch the two radix sorts need for `items` entries (0 if it cannot be
+// queried); the launcher of one rebalancing pass over instance inst, whose
+// state is cell-sorted (it synchronises the stream once, for the list length).
+size_t rb_sort_temp_bytes(int64_t items);
+hipError_t launch_rebalance(const InstDev *insts, InstState *states, int inst, int N, const RbScratch &sc,
+                            hipStream_t st);
 
 // The no-allocation diagnostics (noalloc.hip): a library-owned device array
 // of kNoAllocMaxInst records of kNoAllocRecord words.

@@ -376,10 +376,14 @@ struct DepAcc {
 
 // S2 deposit of one particle into the workgroup's LDS grid (the periodic
 // fold of nodes 0 and N happens when the grid is flushed).
-__device__ __forceinline__ void lds_deposit_s2(int64_t *sA, const GridPar &G, int j, double xi) {
+__device__ __forceinline__ void lds_deposit_s2(int64_t *sA, const GridPar &G, int j, double xi,
+                                               int sh = 0) {
   int n;
   int64_t wl, wc, wr;
   weights_s2(j, xi, n, wl, wc, wr);
+  wl <<= sh;
+  wc <<= sh;
+  wr <<= sh;
   atomicAdd(reinterpret_cast<unsigned long long *>(&sA[fold_s2(n - 1, G.N, G.periodic)]),
             (unsigned long long)wl);
   atomicAdd(reinterpret_cast<unsigned long long *>(&sA[n]), (unsigned long long)wc);
@@ -399,22 +403,28 @@ __device__ __forceinline__ void global_node_add(int64_t *A, const GridPar &G, in
 }
 // A particle created in a pass (ionisation product, secondary electron) goes
 // straight into the deposit of the next step with the instance's shape.
-__device__ __forceinline__ void global_deposit(CInst &I, int64_t *A, int j, double xi) {
+// sh: the power of two of the particle's weight in the deposit's unit.
+__device__ __forceinline__ void global_deposit(CInst &I, int64_t *A, int j, double xi, int sh = 0) {
   const GridPar G = grid_par(I);
   if (I.gather == 2) {
     int n;
     int64_t wl, wc, wr;
     weights_s2(j, xi, n, wl, wc, wr);
-    global_node_add(A, G, fold_s2(n - 1, G.N, G.periodic), wl);
-    global_node_add(A, G, n, wc);
-    global_node_add(A, G, fold_s2(n + 1, G.N, G.periodic), wr);
+    global_node_add(A, G, fold_s2(n - 1, G.N, G.periodic), wl << sh);
+    global_node_add(A, G, n, wc << sh);
+    global_node_add(A, G, fold_s2(n + 1, G.N, G.periodic), wr << sh);
   } else {
     int64_t w0, w1;
     weights(xi, w0, w1);
-    global_node_add(A, G, j, w0);
-    global_node_add(A, G, j + 1, w1);
+    global_node_add(A, G, j, w0 << sh);
+    global_node_add(A, G, j + 1, w1 << sh);
   }
 }
+
+// Power of two of a particle's weight in the unit of the deposit: class - 4
+// plus the instance's unit exponent (0 for every particle of a discharge that
+// is not rebalanced).
+__device__ __forceinline__ int weight_shift(int cls, int wunit) { return cls - kClassUnit + wunit; }
 
 __device__ __forceinline__ void set_status(InstState &S, int bits) {
   atomicOr(&S.status, bits);
@@ -425,11 +435,11 @@ __device__ __forceinline__ bool eedf_due(CInst &I, int64_t k) {
 }
 
 __device__ __forceinline__ void eedf_sample(CInst &I, double x, double vx, double vy,
-                                            double vz) {
+                                            double vz, unsigned long long count = 1ull) {
   if (!(fabs(x - I.eedf_centre) < I.eedf_half)) return;
   const double eps = kHALF_ME_OVER_QE * ((vx * vx + vy * vy) + vz * vz);
   const double b = floor(eps / I.eedf_de);
-  if (b < (double)I.eedf_bins) atomicAdd(&I.eedf[(int)b], 1ull);
+  if (b < (double)I.eedf_bins) atomicAdd(&I.eedf[(int)b], count);
 }
 
 // Reserve a slot for a new particle of species s; -1 when the segment is full.
@@ -492,13 +502,14 @@ struct F64 {
 };
 
 // Write a new particle (SEE electron or ionisation product).
-// k1: the first step the particle takes part in; kn: its first candidacy.
+// k1: the first step the particle takes part in; kn: its first candidacy;
+// cls: its weight class (FP32 form).
 template <class F>
 __device__ void write_new(CInst &I, typename F::View P, int64_t idx, double x, int cell,
                          float off, double vx, double vy, double vz, uint64_t id, int32_t kn,
-                         int64_t k1) {
+                         int64_t k1, int cls) {
   if constexpr (F::prec == 1) {
-    const uint32_t w = hw_encode(cell, kn, k1);
+    const uint32_t w = hw_encode(cell, kn, k1, cls);
     P.hw[idx] = w;
     P.off[idx] = off;
     P.vx[idx] = (float)vx;
@@ -518,7 +529,7 @@ __device__ void write_new(CInst &I, typename F::View P, int64_t idx, double x, i
 // electron goes straight into the electron deposit of step k+1 when `dep`.
 template <class F>
 __device__ void emit_secondary(CInst &I, InstState &S, Smem &sm, uint64_t ion_id, int wall,
-                               int64_t k, int buf, bool dep, int64_t *A_next_e) {
+                               int64_t k, int buf, bool dep, int64_t *A_next_e, int cls) {
   const uint4 r = philox((uint32_t)k, TAG_SEE | (1u << 8), I.seed, ion_id);
   if (!(u32d(r.x) < I.gamma_see)) return;
   const uint4 p = philox((uint32_t)k, TAG_SEE_POS | (1u << 8), I.seed, ion_id);
@@ -545,9 +556,10 @@ __device__ void emit_secondary(CInst &I, InstState &S, Smem &sm, uint64_t ion_id
   }
   const int64_t idx = append_slot(I, S, 0);
   if (idx < 0) return;
-  write_new<F>(I, F::view(I, 0, buf), idx, x, cell, off, vx, I.vt_see * zy, I.vt_see * zz, cid, kn, k + 1);
+  write_new<F>(I, F::view(I, 0, buf), idx, x, cell, off, vx, I.vt_see * zy, I.vt_see * zz, cid, kn, k + 1,
+               cls);
   atomicAdd(&sm.ctr[C_SEE], 1ull);
-  if (dep) global_deposit(I, A_next_e, j, xi);
+  if (dep) global_deposit(I, A_next_e, j, xi, weight_shift(cls, I.wunit));
 }
 
 // ---------------------------------------------------------------------------
@@ -657,7 +669,7 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
   unsigned long long live_here = 0;
   // Per-segment constants, in scalar registers (see GridPar).
   GridPar G{0, 0, 0, 0.0};
-  int gather = 0;
+  int gather = 0, wunit = 0;
   bool coll = false, due_eedf = false;
   float qmdt32 = 0.0f, hq32 = 0.0f;
   double qmdt = 0.0, hq = 0.0, dt = 0.0, L = 0.0;
@@ -728,6 +740,7 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
       const int par = (int)(k & 1);
       G = GridPar{uni(I.N), uni(I.bc == 1 ? 1 : 0), uni(I.uniform), uni(I.dx)};
       gather = uni(I.gather);
+      wunit = uni(I.wunit);
       coll = (MODE == M_MCC || MODE == M_FUSED) && I.nudt[sp] > 0.0;
       due_eedf = (MODE == M_PUSH || MODE == M_FUSED) && sp == 0 && eedf_due(I, k);
       qmdt32 = uni(I.qmdt32[sp]);
@@ -875,19 +888,20 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
           if (live && !gone) {
             const int jj = cn[q];
             const float sig = on[q];
+            const int sh = weight_shift(hw_class(hw[q]), wunit);
             if (due_eedf) {
               const double x = I.uniform ? ((double)jj * I.dx + (double)sig * I.dx)
                                          : (I.nodes[jj] + (double)sig * I.h[jj]);
               if (fabs(x - I.eedf_centre) < I.eedf_half)
-                eedf_sample(I, x, (double)v1, (double)P.cold[ii].vy, (double)P.cold[ii].vz);
+                eedf_sample(I, x, (double)v1, (double)P.cold[ii].vy, (double)P.cold[ii].vz, 1ull << sh);
             }
             if constexpr (MODE == M_FUSED) {
               if (gather == 2) {
-                lds_deposit_s2(sA, G, jj, (double)sig);
+                lds_deposit_s2(sA, G, jj, (double)sig, sh);
               } else {
                 int64_t w0, w1;
                 weights32(sig, w0, w1);
-                dep.add(sA, jj, w0, w1);
+                dep.add(sA, jj, w0 << sh, w1 << sh);
               }
             }
           }
@@ -904,12 +918,13 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
         const int ii = (int)(i0 + q);
         const int j = hw_cell(hw[q]);
         if constexpr (MODE == M_DEPOSIT) {
+          const int sh = weight_shift(hw_class(hw[q]), wunit);
           if (gather == 2) {
-            lds_deposit_s2(sA, G, j, (double)o[q]);
+            lds_deposit_s2(sA, G, j, (double)o[q], sh);
           } else {
             int64_t w0, w1;
             weights32(o[q], w0, w1);
-            dep.add(sA, j, w0, w1);
+            dep.add(sA, j, w0 << sh, w1 << sh);
           }
         } else if constexpr (MODE == M_PULLBACK) {
           const float e = (gather == 0)   ? sE32[j]
@@ -953,7 +968,9 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
         if (__ballot(want[0] || want[1] || want[2] || want[3]) != 0) {
 #pragma unroll
           for (int q = 0; q < kPPT; ++q) {
-            enqueue(want[q], make_int4(went[q], (int)hn[q], __float_as_int(vn[q]), __float_as_int(on[q])));
+            // an absorbed particle's record keeps its last word (its weight class)
+            const uint32_t hrec = ((unsigned)went[q] >> kQShift) != 0u ? hw[q] : hn[q];
+            enqueue(want[q], make_int4(went[q], (int)hrec, __float_as_int(vn[q]), __float_as_int(on[q])));
             spill(false);   // at most 64 more: kSpill - 1 + 64 <= kWaveQ
           }
         }
@@ -1101,7 +1118,8 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
 // Energy and angle histograms of an absorbed particle (species sp, wall wi):
 // energy bin floor(E * bins / emax), the last bin for E >= emax; angle to the
 // wall normal theta = acos(|vx| / |v|), bin floor(theta_deg * abins / 90).
-__device__ __forceinline__ void record_impact(CInst &I, int sp, int wi, double en, double vx, double v2) {
+__device__ __forceinline__ void record_impact(CInst &I, int sp, int wi, double en, double vx, double v2,
+                                              unsigned long long count) {
   const int nb = I.imp_bins, na = I.imp_abins;
   unsigned long long *row = I.impact + (size_t)(2 * sp + wi) * (size_t)(nb + 1 + na);
   const double fe = floor(en * I.imp_escale);
@@ -1109,8 +1127,8 @@ __device__ __forceinline__ void record_impact(CInst &I, int sp, int wi, double e
   const double c = (v2 > 0.0) ? fmin(1.0, fabs(vx) / sqrt(v2)) : 1.0;
   const double th = acos(c) * (180.0 / 3.14159265358979323846);
   const int ba = min((int)floor(th * I.imp_ascale), na - 1);
-  atomicAdd(&row[be], 1ull);
-  atomicAdd(&row[nb + 1 + ba], 1ull);
+  atomicAdd(&row[be], count);
+  atomicAdd(&row[nb + 1 + ba], count);
 }
 
 // Velocity and id of a queued particle: vx from its queue record, the rest
@@ -1152,7 +1170,7 @@ __device__ void drain_one(CInst &I, InstState &S, Smem &sm, int sp, int buf, int
     if (kind == 0 && hw_far(hw)) {
       const int32_t kf = P.knext[i];
       if ((int64_t)kf > k) {
-        P.hw[i] = hw_encode(hw_cell(hw), kf, k + 1);
+        P.hw[i] = hw_encode(hw_cell(hw), kf, k + 1, hw_class(hw));
         return;
       }
     }
@@ -1160,16 +1178,19 @@ __device__ void drain_one(CInst &I, InstState &S, Smem &sm, int sp, int buf, int
   double vxd, vy, vz;
   uint64_t id;
   load_particle(P, i, rec, vxd, vy, vz, id);
+  // the particle's weight class (its record's word; FP64: class 4)
+  const int cls = (F::prec == 1) ? hw_class((uint32_t)rec.y) : kClassUnit;
+  const int sh = weight_shift(cls, I.wunit);
   if (kind != 0) {
     const int wi = kind - 1;
     atomicAdd(&sm.ctr[C_ABS + 2 * sp + wi], 1ull);
     const double v2 = (vxd * vxd + vy * vy) + vz * vz;
     const double en = (0.5 * I.mass[sp] / kQE) * v2;
-    atomicAdd(&sm.ctr[C_EABS + 2 * sp + wi], (unsigned long long)rint(en * 65536.0));
-    if (I.avg_every > 0 && k >= I.avg_start) record_impact(I, sp, wi, en, vxd, v2);
+    atomicAdd(&sm.ctr[C_EABS + 2 * sp + wi], (unsigned long long)rint(en * 65536.0) << sh);
+    if (I.avg_every > 0 && k >= I.avg_start) record_impact(I, sp, wi, en, vxd, v2, 1ull << sh);
     if (sp == 1 && I.gamma_see > 0.0 && I.nsp > 1)
       emit_secondary<F>(I, S, sm, id, wi == 0 ? -1 : 1, k, buf, MODE == M_FUSED,
-                        I.A[(k + 1) & 1][0]);
+                        I.A[(k + 1) & 1][0], cls);
     return;
   }
   double ux = vxd, uy = vy, uz = vz;
@@ -1198,12 +1219,13 @@ __device__ void drain_one(CInst &I, InstState &S, Smem &sm, int sp, int buf, int
       } else {
         xx = P.x[i];
       }
+      // the pair carries the primary's weight
       if (ie >= 0)
         write_new<F>(I, P, ie, xx, cc, oo, ej[0], ej[1], ej[2], eid,
-                     next_candidate(eid, k, 0, I.seed, I.nudt[0]), k + 1);
+                     next_candidate(eid, k, 0, I.seed, I.nudt[0]), k + 1, cls);
       if (ii >= 0)
         write_new<F>(I, F::view(I, 1, buf), ii, xx, cc, oo, gx, gy, gz, iid,
-                     next_candidate(iid, k, 1, I.seed, I.nudt[1]), k + 1);
+                     next_candidate(iid, k, 1, I.seed, I.nudt[1]), k + 1, cls);
       if constexpr (MODE == M_FUSED) {
         int j;
         double xi;
@@ -1214,8 +1236,8 @@ __device__ void drain_one(CInst &I, InstState &S, Smem &sm, int sp, int buf, int
           j = locate64(grid_par(I), I.nodes, xx, xi);
         }
         const int par1 = (int)((k + 1) & 1);
-        if (ie >= 0) global_deposit(I, I.A[par1][0], j, xi);
-        if (ii >= 0) global_deposit(I, I.A[par1][1], j, xi);
+        if (ie >= 0) global_deposit(I, I.A[par1][0], j, xi, sh);
+        if (ii >= 0) global_deposit(I, I.A[par1][1], j, xi, sh);
       }
     }
   } else {
@@ -1237,7 +1259,7 @@ __device__ void drain_one(CInst &I, InstState &S, Smem &sm, int sp, int buf, int
   }
   const int32_t kn = next_candidate(id, k, sp, I.seed, I.nudt[sp]);
   if constexpr (F::prec == 1) {
-    const uint32_t w = hw_encode(hw_cell((uint32_t)rec.y), kn, k + 1);
+    const uint32_t w = hw_encode(hw_cell((uint32_t)rec.y), kn, k + 1, cls);
     P.hw[i] = w;
     if (hw_far(w)) P.knext[i] = kn;
   } else {
@@ -1325,7 +1347,7 @@ k_init(const InstDev *__restrict__ insts, InstState *__restrict__ states, int in
   int cell = 0;
   float off = 0.0f;
   if constexpr (F::prec == 1) to_state32(I, x, cell, off);
-  write_new<F>(I, P, i, x, cell, off, vx, vy, vz, id, kn, 0);
+  write_new<F>(I, P, i, x, cell, off, vx, vy, vz, id, kn, 0, kClassUnit);
 }
 
 // ---------------------------------------------------------------------------
@@ -1341,29 +1363,35 @@ k_diag(const InstDev *__restrict__ insts, const InstState *__restrict__ states, 
   for (int s = 0; s < I.nsp; ++s) {
     typename F::View P = F::view(I, s, S.parity);
     const int64_t ext = S.extent[s];
-    unsigned long long live = 0, ke = 0;
+    unsigned long long live = 0, ke = 0, wsum = 0;
     double vmax = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ext;
          i += (int64_t)gridDim.x * blockDim.x) {
       double vx, vy, vz;
+      int sh = 0;
       if constexpr (F::prec == 1) {
-        if (!hw_live(P.hw[i])) continue;
+        const uint32_t w = P.hw[i];
+        if (!hw_live(w)) continue;
+        sh = weight_shift(hw_class(w), I.wunit);
         vx = P.vx[i]; vy = P.cold[i].vy; vz = P.cold[i].vz;
       } else {
         if (!(P.x[i] >= 0.0)) continue;
         vx = P.vx[i]; vy = P.vy[i]; vz = P.vz[i];
       }
       live += 1;
+      wsum += 1ull << sh;
       const double en = (0.5 * I.mass[s] / kQE) * ((vx * vx + vy * vy) + vz * vz);
-      ke += (unsigned long long)rint(en * 1048576.0);
+      ke += (unsigned long long)rint(en * 1048576.0) << sh;
       vmax = fmax(vmax, fabs(vx));
     }
     live = wave_sum_u64(live);
     ke = wave_sum_u64(ke);
+    wsum = wave_sum_u64(wsum);
     for (int o = 32; o > 0; o >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, o, 64));
     if (__lane_id() == 0) {
       atomicAdd(&out[D_LIVE0 + s], live);
       atomicAdd(&out[D_KE0 + s], ke);
+      if (s == 0) atomicAdd(&out[D_WE], wsum);
       if (s == 0) atomicMax(&out[D_VMAX], (unsigned long long)__double_as_longlong(vmax));
     }
   }
@@ -1414,7 +1442,7 @@ k_moments(const InstDev *__restrict__ insts, const InstState *__restrict__ state
   tile_prefix(prefix, nseg);
   const int64_t T = prefix[nseg];
   const int64_t t0 = T * blockIdx.x / gridDim.x, t1 = T * (blockIdx.x + 1) / gridDim.x;
-  int seg = -1, N = 0, gather = 0;
+  int seg = -1, N = 0, gather = 0, wu = 0;
   CInst *Ip = nullptr;
   int64_t ext = 0;
   typename F::View P;
@@ -1447,6 +1475,7 @@ k_moments(const InstDev *__restrict__ insts, const InstState *__restrict__ state
       const InstState &S = states[seg >> 1];
       N = I.N;
       gather = I.gather;
+      wu = I.wunit;
       G = grid_par(I);
       ext = uni((int64_t)S.extent[seg & 1]);
       P = F::view(I, seg & 1, S.parity);
@@ -1462,7 +1491,7 @@ k_moments(const InstDev *__restrict__ insts, const InstState *__restrict__ state
       const int64_t i = base + q * BLOCK + t;
       bool ok = i < ext;
       int j = 0;
-      double xi = 0.0, vx = 0.0;
+      double xi = 0.0, vx = 0.0, fw = 1.0;   // fw: the particle's weight in deposit units
       if (ok) {
         if constexpr (F::prec == 1) {
           const uint32_t w = P.hw[i];
@@ -1471,6 +1500,7 @@ k_moments(const InstDev *__restrict__ insts, const InstState *__restrict__ state
           if (ok) {
             xi = (double)P.off[i];
             vx = (double)P.vx[i];
+            fw = ldexp(1.0, weight_shift(hw_class(w), wu));
           }
         } else {
           const double x = P.x[i];
@@ -1487,8 +1517,8 @@ k_moments(const InstDev *__restrict__ insts, const InstState *__restrict__ state
         const int n = up ? j + 1 : j;
         const double a = up ? 1.5 - xi : 0.5 - xi;
         const double b = up ? xi - 0.5 : 0.5 + xi;
-        const double wl = 0.5 * (a * a), wr = 0.5 * (b * b);
-        const double wc = (1.0 - wl) - wr;
+        const double wl = fw * (0.5 * (a * a)), wr = fw * (0.5 * (b * b));
+        const double wc = fw * ((1.0 - 0.5 * (a * a)) - 0.5 * (b * b));
         const int nl = fold_s2(n - 1, N, G.periodic), nr = fold_s2(n + 1, N, G.periodic);
         const double v2 = vx * vx;
         atomicAdd(&m1[nl], wl * vx);
@@ -1497,18 +1527,18 @@ k_moments(const InstDev *__restrict__ insts, const InstState *__restrict__ state
         atomicAdd(&m2[nl], wl * v2);
         atomicAdd(&m2[n], wc * v2);
         atomicAdd(&m2[nr], wr * v2);
-        atomicAdd(&pw[j], vx * gather_ec2_64(sE, j, xi));
+        atomicAdd(&pw[j], fw * (vx * gather_ec2_64(sE, j, xi)));
         ok = false;
       }
       double a0 = 0.0, a1 = 0.0, b0 = 0.0, b1 = 0.0, pp = 0.0;
       if (ok) {
-        const double w0 = 1.0 - xi, w1 = xi;
+        const double w0 = fw * (1.0 - xi), w1 = fw * xi;
         a0 = w0 * vx;
         a1 = w1 * vx;
         b0 = w0 * (vx * vx);
         b1 = w1 * (vx * vx);
         const double e = (gather == 0) ? sE[j] : (1.0 - xi) * sE[j] + xi * sE[j + 1];
-        pp = vx * e;
+        pp = fw * (vx * e);
       }
       // A cell-sorted state puts whole wavefronts in one cell: then the
       // wavefront sums its terms and one lane adds them (same-address LDS
@@ -1557,7 +1587,7 @@ k_reencode(const InstDev *__restrict__ insts, const InstState *__restrict__ stat
       const uint32_t w = P.hw[i];
       if (!hw_live(w)) continue;
       const int64_t kn = hw_knext(w, hw_far(w) ? P.knext[i] : 0, k0);
-      const uint32_t nw = hw_encode(hw_cell(w), kn, k1);
+      const uint32_t nw = hw_encode(hw_cell(w), kn, k1, hw_class(w));
       P.hw[i] = nw;
       if (hw_far(nw)) P.knext[i] = (int32_t)kn;
     }

@@ -1,10 +1,10 @@
-"""The FP32 form's collision countdown (a 19-bit count of steps in each
+"""The FP32 form's collision countdown (a 16-bit count of steps in each
 particle's hot word, with the far flag and the knext array for candidacies
 beyond its range) against the oracle's absolute candidate steps.
 
 A periodic electron box at very low pressure (waits of ~1e8 steps) is set to
 candidacies spread around the count's range, set_step moves it to k0, it is
-advanced 2^19 - 9 steps on the GPU, and then the oracle and the GPU advance
+advanced 2^16 - 9 steps on the GPU, and then the oracle and the GPU advance
 together across the step where the far countdowns run out: every candidacy
 happens at its step, every far particle keeps its candidacy (false alarms are
 not candidates), and the state matches the oracle's by id.
@@ -19,7 +19,7 @@ from gpu_common import compare_species, oracle_from_states, species_dict
 
 pytestmark = pytest.mark.gpu
 
-CNT_MAX = 2 ** 19 - 1
+CNT_MAX = 2 ** 16 - 1
 K0 = 100
 INT32_MAX = 2 ** 31 - 1
 
@@ -63,7 +63,7 @@ def test_countdown_across_its_range(gpu):
     assert np.array_equal(kept[~due], kn[os_][~due])
     assert np.all(kept[due] >= k1)
     note("at", k1, "candidates", int(d["candidates"][0]))
-    # the oracle and the GPU across k0 + 2^19 - 1 (where far countdowns end)
+    # the oracle and the GPU across k0 + 2^16 - 1 (where far countdowns end)
     ref = oracle_from_states(cfg, [g1], k1)
     ctx2 = Context([cfg])
     ctx2.set_state(0, 0, g1)

@@ -35,7 +35,7 @@ def test_binding_covers_the_header():
 
 
 def test_abi_version_and_status_strings(lib):
-    assert lib.pic_abi_version() == 5
+    assert lib.pic_abi_version() == 6
     assert lib.pic_status_string(0) == b"ok"
 
 
@@ -51,7 +51,9 @@ def cfg(**over):
                                  dict(capacity=10), dict(gamma_see=1.5), dict(eedf_bins=-1),
                                  dict(nodes=np.array([0.0, 0.2, 0.1, 0.3]), n_cells=3),
                                  dict(nodes=np.array([0.1, 0.2, 0.3]), n_cells=2),
-                                 dict(weight_m2=0.0, n0_m3=0.0)])
+                                 dict(weight_m2=0.0, n0_m3=0.0),
+                                 dict(rebalance_ppc=-1), dict(rebalance_ppc=100, precision=0),
+                                 dict(rebalance_ppc=100, precision=1, rebalance_dv_e=-1.0)])
 def test_invalid_config_is_rejected_before_any_device_call(lib, bad):
     from paper_2308_13092_amd._lib import make_config, pic_config
     keep = []
