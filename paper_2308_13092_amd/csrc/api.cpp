@@ -1027,7 +1027,8 @@ pic_status pic_diagnostics(pic_ctx *c, int32_t inst, pic_diag *out) {
   if (r != PIC_OK) return r;
   if (!out) return fail(c, PIC_EINVAL, "null output");
   HIP_TRY(c, hipMemsetAsync(c->d_diag, 0, 8 * D_NWORDS, c->stream));
-  launch_diag(c->d_inst, c->d_state, inst, c->prec, c->d_diag, c->stream);
+  launch_diag(c->d_inst, c->d_state, inst, c->prec, std::max(c->host_inst[inst].cap[0], c->host_inst[inst].cap[1]),
+              c->d_diag, c->stream);
   HIP_TRY(c, hipGetLastError());
   unsigned long long w[D_NWORDS];
   HIP_TRY(c, hipMemcpyAsync(w, c->d_diag, sizeof w, hipMemcpyDeviceToHost, c->stream));
@@ -1066,7 +1067,8 @@ pic_status pic_diagnostics_noalloc(pic_ctx *c, const int32_t *insts, int32_t n, 
   launch_fill_zero(scr, n * kNoAllocRecord, st);
   for (int i = 0; i < n; ++i) {
     unsigned long long *rec = scr + (size_t)i * kNoAllocRecord;
-    launch_diag(c->d_inst, c->d_state, insts[i], c->prec, rec, st);
+    launch_diag(c->d_inst, c->d_state, insts[i], c->prec,
+                std::max(c->host_inst[insts[i]].cap[0], c->host_inst[insts[i]].cap[1]), rec, st);
     launch_deposit_total(c->d_inst, c->d_state, insts[i], rec, st);
   }
   HIP_TRY(c, hipGetLastError());

@@ -39,7 +39,7 @@ hipError_t launch_drain(const InstDev *insts, InstState *states, int n_inst, int
 int drain_blocks_per_cu(int prec, int mode);
 hipError_t launch_sort(const InstDev *insts, InstState *states, int n_inst, int prec, int grid,
                        int max_n, hipStream_t s);
-void launch_diag(const InstDev *insts, InstState *states, int inst, int prec,
+void launch_diag(const InstDev *insts, InstState *states, int inst, int prec, int64_t max_particles,
                  unsigned long long *out, hipStream_t s);
 void launch_zero_deposit(const InstDev *insts, InstState *states, int n_inst, hipStream_t s);
 // FP32 form: re-express instance inst's countdowns from step k1 (was k0).

@@ -1358,8 +1358,13 @@ template <class F>
 __global__ void __launch_bounds__(256)
 k_diag(const InstDev *__restrict__ insts, const InstState *__restrict__ states, int inst,
        unsigned long long *__restrict__ out) {
+  // Wavefront sums, then block sums in LDS: one atomic per block and
+  // quantity (same-address atomics from every wavefront would serialise).
+  __shared__ unsigned long long red[4][3];
+  __shared__ double redv[4];
   CInst &I = cinst(insts)[inst];
   const InstState &S = states[inst];
+  const int wave = threadIdx.x >> 6;
   for (int s = 0; s < I.nsp; ++s) {
     typename F::View P = F::view(I, s, S.parity);
     const int64_t ext = S.extent[s];
@@ -1389,11 +1394,28 @@ k_diag(const InstDev *__restrict__ insts, const InstState *__restrict__ states, 
     wsum = wave_sum_u64(wsum);
     for (int o = 32; o > 0; o >>= 1) vmax = fmax(vmax, __shfl_xor(vmax, o, 64));
     if (__lane_id() == 0) {
-      atomicAdd(&out[D_LIVE0 + s], live);
-      atomicAdd(&out[D_KE0 + s], ke);
-      if (s == 0) atomicAdd(&out[D_WE], wsum);
-      if (s == 0) atomicMax(&out[D_VMAX], (unsigned long long)__double_as_longlong(vmax));
+      red[wave][0] = live;
+      red[wave][1] = ke;
+      red[wave][2] = wsum;
+      redv[wave] = vmax;
     }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int nw = (int)(blockDim.x >> 6);
+      for (int w = 1; w < nw; ++w) {
+        live += red[w][0];
+        ke += red[w][1];
+        wsum += red[w][2];
+        vmax = fmax(vmax, redv[w]);
+      }
+      if (live) {
+        atomicAdd(&out[D_LIVE0 + s], live);
+        atomicAdd(&out[D_KE0 + s], ke);
+        if (s == 0) atomicAdd(&out[D_WE], wsum);
+        if (s == 0) atomicMax(&out[D_VMAX], (unsigned long long)__double_as_longlong(vmax));
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -1710,12 +1732,15 @@ void launch_init(const InstDev *insts, InstState *states, int inst, int species,
     hipLaunchKernelGGL(k_init<F64>, dim3(blocks), dim3(256), 0, s, insts, states, inst, species, t_ev);
 }
 
-void launch_diag(const InstDev *insts, InstState *states, int inst, int prec,
+void launch_diag(const InstDev *insts, InstState *states, int inst, int prec, int64_t max_particles,
                  unsigned long long *out, hipStream_t s) {
+  // About 16 particles per thread, at most 256 blocks.
+  const int64_t b = (max_particles + 4095) / 4096;
+  const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(256, b)));
   if (prec == 1)
-    hipLaunchKernelGGL(k_diag<F32>, dim3(1024), dim3(256), 0, s, insts, states, inst, out);
+    hipLaunchKernelGGL(k_diag<F32>, grid, dim3(256), 0, s, insts, states, inst, out);
   else
-    hipLaunchKernelGGL(k_diag<F64>, dim3(1024), dim3(256), 0, s, insts, states, inst, out);
+    hipLaunchKernelGGL(k_diag<F64>, grid, dim3(256), 0, s, insts, states, inst, out);
 }
 
 void launch_moments(const InstDev *insts, InstState *states, int n_inst, int prec, int grid, int max_n,

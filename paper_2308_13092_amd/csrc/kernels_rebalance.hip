@@ -58,32 +58,63 @@ k_rb_flags(const InstDev *__restrict__ insts, int inst) {
     }
 }
 
-// The merge candidates: (id, species << 31 | index), in any order.
+// The merge candidates: (id, species << 31 | index), in any order.  Each
+// block takes chunks of kRbChunk particles and reserves the list positions of
+// a whole chunk with one atomic (one per wavefront would serialise on the
+// counter when most particles are candidates).
+constexpr int kRbPer = 16;
+constexpr int kRbChunk = 256 * kRbPer;
+
 __global__ void __launch_bounds__(256)
 k_rb_collect(const InstDev *__restrict__ insts, const InstState *__restrict__ states, int inst,
              unsigned long long *__restrict__ keys, uint32_t *__restrict__ vals,
              unsigned long long *__restrict__ count) {
+  __shared__ unsigned long long wsum[4];
+  __shared__ unsigned long long base;
   CInst &I = cinst(insts)[inst];
   const InstState &S = states[inst];
+  const int lane = __lane_id();
+  const int wave = threadIdx.x >> 6;
+  const unsigned long long below = (1ull << lane) - 1ull;
   for (int s = 0; s < I.nsp; ++s) {
     const P32 P = view32(I.pbuf[s][S.parity], I.cap[s]);
     const int64_t ext = S.extent[s];
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ext;
-         i += (int64_t)gridDim.x * blockDim.x) {
-      const uint32_t w = P.hw[i];
-      const bool want = hw_live(w) && hw_class(w) < kClassMax && I.rb_flag[s][hw_cell(w)] == 1;
-      const unsigned long long m = __ballot(want);
-      if (m == 0) continue;
-      const int lane = __lane_id();
-      const int leader = __ffsll((long long)m) - 1;
-      unsigned long long b = 0;
-      if (lane == leader) b = atomicAdd(count, (unsigned long long)__popcll(m));
-      b = __shfl(b, leader, 64);
-      if (want) {
-        const unsigned long long at = b + (unsigned long long)__popcll(m & ((1ull << lane) - 1ull));
-        keys[at] = P.cold[i].id;
-        vals[at] = ((uint32_t)s << 31) | (uint32_t)i;
+    for (int64_t c0 = (int64_t)blockIdx.x * kRbChunk; c0 < ext; c0 += (int64_t)gridDim.x * kRbChunk) {
+      // this wavefront's slice of the chunk: kRbPer rows of 64 particles
+      const int64_t w0 = c0 + (int64_t)wave * 64 * kRbPer;
+      unsigned long long m[kRbPer];
+      unsigned long long n_w = 0;
+#pragma unroll
+      for (int r = 0; r < kRbPer; ++r) {
+        const int64_t i = w0 + (int64_t)r * 64 + lane;
+        bool want = false;
+        if (i < ext) {
+          const uint32_t w = P.hw[i];
+          want = hw_live(w) && hw_class(w) < kClassMax && I.rb_flag[s][hw_cell(w)] == 1;
+        }
+        m[r] = __ballot(want);
+        n_w += (unsigned long long)__popcll(m[r]);
       }
+      if (lane == 0) wsum[wave] = n_w;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        const unsigned long long t = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        base = t ? atomicAdd(count, t) : 0ull;
+      }
+      __syncthreads();
+      unsigned long long at = base;
+      for (int v = 0; v < wave; ++v) at += wsum[v];
+#pragma unroll
+      for (int r = 0; r < kRbPer; ++r) {
+        if ((m[r] >> lane) & 1ull) {
+          const int64_t i = w0 + (int64_t)r * 64 + lane;
+          const unsigned long long q = at + (unsigned long long)__popcll(m[r] & below);
+          keys[q] = P.cold[i].id;
+          vals[q] = ((uint32_t)s << 31) | (uint32_t)i;
+        }
+        at += (unsigned long long)__popcll(m[r]);
+      }
+      __syncthreads();   // wsum and base are rewritten by the next chunk
     }
   }
 }
@@ -103,15 +134,27 @@ k_rb_keys(const InstDev *__restrict__ insts, const InstState *__restrict__ state
   }
 }
 
-// First index of keys[0..n) not below x (lower) / above x (upper).
-__device__ __forceinline__ int64_t lower_bound_u32(const uint32_t *keys, int64_t n, uint32_t x, bool upper) {
-  int64_t lo = 0, hi = n;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (upper ? keys[mid] <= x : keys[mid] < x) lo = mid + 1;
-    else hi = mid;
+// First index of the run of keys equal to keys[j] (keys sorted): a backward
+// search in doubling steps, then bisection -- its loads stay near j.
+__device__ __forceinline__ int64_t run_start(const uint32_t *keys, int64_t j) {
+  const uint32_t key = keys[j];
+  int64_t a = j;        // keys[a] == key
+  int64_t b = -1;       // keys[b] != key, or b = -1
+  for (int64_t step = 1;; step <<= 1) {
+    const int64_t p = j - step;
+    if (p < 0) break;
+    if (keys[p] != key) {
+      b = p;
+      break;
+    }
+    a = p;
   }
-  return lo;
+  while (a - b > 1) {
+    const int64_t mid = b + ((a - b) >> 1);
+    if (keys[mid] == key) a = mid;
+    else b = mid;
+  }
+  return a;
 }
 
 // One thread per list position: the first of every full quadruple of its
@@ -124,10 +167,10 @@ k_rb_merge(const InstDev *__restrict__ insts, InstState *__restrict__ states, in
   unsigned long long merges[2] = {0, 0};
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t key = k32[j];
-    const int64_t lo = lower_bound_u32(k32, n, key, false);
-    const int64_t hi = lower_bound_u32(k32, n, key, true);
-    const int64_t pos = j - lo;
-    if ((pos & 3) != 0 || pos + 4 > hi - lo) continue;
+    // a full quadruple starts here: j + 3 is in the same group, and j is at
+    // a multiple of 4 from the group's start
+    if (j + 3 >= n || k32[j + 3] != key) continue;
+    if (((j - run_start(k32, j)) & 3) != 0) continue;
     const int s = (int)(vals[j] >> 31);
     const P32 P = view32(I.pbuf[s][S.parity], I.cap[s]);
     int64_t q[4];
