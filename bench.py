@@ -216,7 +216,8 @@ def run_serving_matched(n_req, rho, capacity, slots=256, seed=13093):
                mean_request_particle_steps=mean_work,
                trace=(f"first {n_req} requests of the seeded stream (seed {seed}): 64-2048 cells, "
                       f"1e5-8e6 particles (log-uniform), 100-500 V, 10-100 mTorr, 50-500 RF cycles, "
-                      f"dt = T_RF/(400-1000), FP32 state; arrivals Poisson at {rate:.4g}/s instead of "
+                      f"dt = T_RF/(400-1000), FP32 state, capacity 8x the initial particles; "
+                      f"arrivals Poisson at {rate:.4g}/s instead of "
                       f"20/s, so that the offered load is {rho} x the measured sweep capacity "
                       f"({capacity:.4g} particle-steps/s); request sizes as stated"))
     return out

@@ -146,8 +146,10 @@ typedef struct pic_diag {
   int64_t n_live[2];             /* live macro-particles [electrons, ions]             */
   int64_t extent[2];             /* occupied slots (live + absorbed not yet compacted) */
   int64_t deposit_total[2];      /* sum over nodes of the deposit A_s, in 2^-32 units:
-                                    equals n_live * 2^32 exactly (charge is exact)     */
-  double kinetic_j_m2[2];        /* W sum (m/2)|v|^2, from a 2^-20 eV fixed-point sum   */
+                                    exactly 2^32 times the live particles' summed weight
+                                    in deposit units (W; W/16 when rebalanced)         */
+  double kinetic_j_m2[2];        /* sum of weight x (m/2)|v|^2, from a 2^-20 eV
+                                    fixed-point sum                                    */
   double field_j_m2;             /* (eps0/2) sum_j h_j E_j^2 at the last field solve    */
   int64_t absorbed[2][2];        /* [species][0 left (powered), 1 right] electrode     */
   double absorbed_energy_ev[2][2]; /* energy carried into each electrode (eV, 2^-16 eV) */

@@ -110,8 +110,15 @@ def sweep(n=256, master_seed=13092, precision=1, scale=1.0):
     return out
 
 
-def stream(n=256, master_seed=13093, rate=20.0, precision=1, scale=1.0, cycles=(50, 500)):
-    """Workload 5: (arrival time, config, steps) of n requests."""
+def stream(n=256, master_seed=13093, rate=20.0, precision=1, scale=1.0, cycles=(50, 500),
+           headroom=8):
+    """Workload 5: (arrival time, config, steps) of n requests.
+
+    A served discharge starts at 1e15 m^-3 and, at high pressure and voltage,
+    ionises its way to a density several times higher over its hundreds of RF
+    cycles; each request's particle capacity is ``headroom`` times its initial
+    count, so that such growth fits (a request that still outgrows it ends
+    with PIC_ECAPACITY)."""
     g = np.random.Generator(np.random.PCG64(master_seed))
     t = 0.0
     out = []
@@ -126,7 +133,8 @@ def stream(n=256, master_seed=13093, rate=20.0, precision=1, scale=1.0, cycles=(
         ncyc = int(g.integers(cycles[0], cycles[1] + 1))
         steps = ncyc * div
         cfg = base(n_cells=cells, gap_m=0.025, n0_m3=1e15, v_rf=v, p_pa=p * MTORR,
-                   n_per_species=per, dt_s=T_RF / div, precision=precision, seed=master_seed + i,
+                   n_per_species=per, capacity=headroom * per + 4096, dt_s=T_RF / div,
+                   precision=precision, seed=master_seed + i,
                    sort_interval=20, avg_every=1, avg_start=max(0, steps - 10 * div),
                    eedf_every=max(1, div // 10), k_stop=steps)
         out.append((t, cfg, steps))

@@ -165,6 +165,11 @@ def summarise(reqs, wall_s):
     return dict(requests=len(reqs), completed=len(done),
                 rejected=sum(r.status == "rejected" for r in reqs),
                 failed=sum(r.status == "failed" for r in reqs),
+                failures=[dict(rid=r.rid, status=r.result.get("status"), step=r.result.get("step"),
+                               steps=r.steps, cells=r.cfg.get("n_cells"),
+                               n_per_species=r.cfg.get("n_per_species"), v_rf=r.cfg.get("v_rf"),
+                               p_pa=r.cfg.get("p_pa"))
+                          for r in reqs if r.status == "failed"],
                 p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
                 mean_queue_s=float(np.mean([r.admitted - r.arrival for r in done])) if done else None,
                 particle_steps=int(ps), wall_s=wall_s,
