@@ -3,7 +3,7 @@
 Test infrastructure only (see ``oracle/__init__.py``).
 
 The paper does not say how random numbers are drawn for its Monte-Carlo
-collisions (Section 2, "Methodology"; Section 2a, step 6).  This oracle fixes a
+collisions (Section 2, "Methodology"; Section 2a).  This oracle fixes a
 counter-based contract so that collisions are reproducible and independent of
 particle order: every draw is one Philox block keyed by the particle id and
 counted by (step, tag, seed).  Philox is the generator of Salmon et al.,

@@ -25,7 +25,7 @@ silent the reading taken is stated in the docstring; the readings are:
   nodes closed by Gauss's law on the half cell; MC gather uses S1 (Eq 3).
 * Leapfrog (Eqs 8-9).  The initial velocity is used as v^{-1/2} unless the
   pull-back switch is set.
-* Collisions (Section 2, step 6 of Section 2a): null collisions after the push,
+* Collisions (Sections 2 and 2a): null collisions after the push,
   with the candidate steps drawn as exponential waiting times (equivalent in
   law to a per-step test with probability 1 - exp(-nu_max dt)).
 * Secondary emission (not in the paper): an absorbed ion emits an electron at

@@ -5,7 +5,7 @@ Test infrastructure only (see ``oracle/__init__.py``).
 ``Sim.step`` follows the loop of Section 2a in its order: deposit x^k (Eqs
 2-3), solve Poisson at t_k (Eq 4), form the field (Eq 5, or the centred MC
 field), gather and push (Eqs 6-9) with absorption at the electrodes and
-secondary emission, then collide (step 6) and advance k.  The RF-averaged
+secondary emission, then collide with the gas and advance k.  The RF-averaged
 moments of Section 3a (density and potential every ``avg_every`` steps, the
 central EEDF every ``eedf_every`` steps) accumulate along the way.
 
@@ -134,7 +134,7 @@ class Sim:
         else:
             self.sp = list(species)
 
-    # -- steps 1-3 --------------------------------------------------------
+    # -- deposit, field solve, field ----------------------------------------
     def deposit(self):
         self.A = [deposit_species(self.grid, sp, self.gather, self.u) for sp in self.sp]
         return self.A

@@ -13,7 +13,7 @@
 //               the node deposit, flushed to HBM with int64 atomics.
 //   M_PUSH      Eqs 6-9: gather E^k, leapfrog, absorption at the electrodes,
 //               secondary emission, central EEDF sample.
-//   M_MCC       step 6: null collisions of the particles due this step,
+//   M_MCC       Section 2a collisions: null collisions of the particles due this step,
 //               ionisation pairs appended, then k <- k+1.
 //   M_FUSED     M_PUSH + M_MCC + the deposit of x^{k+1}, in one pass.
 //   M_PULLBACK  v^{-1/2} = v^0 - (q/m) E^0 dt/2 (initial-state option).
