@@ -227,8 +227,11 @@ __device__ __forceinline__ void load_recs(const P32 &P, int64_t i0, int64_t ext,
   if (i0 + 4 <= ext) {
     const int4 c = gload4(reinterpret_cast<const int *>(P.hw) + i0);
     const float4 o = gload4(P.off + i0), x = gload4(P.vx + i0);
-    const int4 k = gload4(P.knext + i0);
     const uint32_t cc[4] = {(uint32_t)c.x, (uint32_t)c.y, (uint32_t)c.z, (uint32_t)c.w};
+    // knext matters only for far particles (see hw_encode): the others'
+    // entries are neither read nor moved
+    int4 k = make_int4(0, 0, 0, 0);
+    if (hw_far(cc[0]) || hw_far(cc[1]) || hw_far(cc[2]) || hw_far(cc[3])) k = gload4(P.knext + i0);
     const float oo[4] = {o.x, o.y, o.z, o.w}, xx[4] = {x.x, x.y, x.z, x.w};
     const int kk[4] = {k.x, k.y, k.z, k.w};
 #pragma unroll
@@ -246,8 +249,9 @@ __device__ __forceinline__ void load_recs(const P32 &P, int64_t i0, int64_t ext,
       r[q] = Rec32{kHwDead, 0.0f, 0.0f, 0.0f, 0.0f, 0, 0u, 0u};
       if (ok[q]) {
         const ecpic_iv4 cd = *(const ECPIC_GLOBAL ecpic_iv4 *)(P.cold + i);
-        r[q] = Rec32{P.hw[i], P.off[i], P.vx[i], __int_as_float(cd.x), __int_as_float(cd.y),
-                     P.knext[i], (uint32_t)cd.z, (uint32_t)cd.w};
+        const uint32_t w = P.hw[i];
+        r[q] = Rec32{w, P.off[i], P.vx[i], __int_as_float(cd.x), __int_as_float(cd.y),
+                     hw_far(w) ? P.knext[i] : 0, (uint32_t)cd.z, (uint32_t)cd.w};
       }
     }
   }
@@ -287,7 +291,7 @@ __device__ __forceinline__ void store_rec(const P32 &P, int64_t d, const Rec32 &
   gstore<uint32_t>(P.hw + d, r.hw);
   gstore<float>(P.off + d, r.off);
   gstore<float>(P.vx + d, r.vx);
-  gstore<int>(P.knext + d, r.knext);
+  if (hw_far(r.hw)) gstore<int>(P.knext + d, r.knext);
   const ecpic_iv4 cd = {__float_as_int(r.vy), __float_as_int(r.vz), (int)r.id_lo, (int)r.id_hi};
   *(ECPIC_GLOBAL ecpic_iv4 *)(P.cold + d) = cd;
 }
