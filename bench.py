@@ -321,7 +321,9 @@ def main():
                     kernel=f"k_particles<F32, M_FUSED, {r32['tuning']['block']}>", avg_launch_ms=round(avg_ms, 4),
                     particles_per_launch=round(per_launch, 1), bytes_per_particle_step=B_ALG[1],
                     step_achieved=round(step_achieved, 1), step_frac=round(step_achieved / HBM_PEAK_GBS, 4),
+                    kernel_frac=round(achieved / HBM_PEAK_GBS, 4),
                     traffic_gbs=(None if traffic is None else round(traffic / (avg_ms * 1e-3) / 1e9, 1)),
+                    traffic_frac=(None if traffic is None else round(traffic / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)),
                     field_ms_per_launch=round(kt["field_ms"] / max(kt["field_launches"], 1), 4),
                     drain_ms_per_launch=round(kt["drain_ms"] / max(kt["drain_launches"], 1), 4),
                     sort_ms_per_launch=round(kt["sort_ms"] / max(kt["sort_launches"], 1), 4),

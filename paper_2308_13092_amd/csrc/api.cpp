@@ -254,6 +254,7 @@ struct pic_ctx {
   unsigned long long *d_diag = nullptr;
   int max_n = 2;
   int field_classes = 0;   // field_class bits of the used slots
+  bool inline_drain = false;   // fused passes drain in the particle kernel (small contexts)
   // 1024 threads per block: measured fastest on the large workload.  Plain
   // launches: on every workload measured they beat graph replay (by about
   // 10 % on the small and resolved discharges, 1 % on the large one).
@@ -311,6 +312,10 @@ static void recompute_max_n(pic_ctx *c) {
       c->field_classes |= field_class((int)s.cfg.n_cells);
     }
   c->max_n = (m + 3) / 4 * 4;
+  int64_t slots_total = 0;
+  for (int i = 0; i < c->n_inst && i < (int)c->host_inst.size(); ++i)
+    if (c->slots[i].used) slots_total += c->host_inst[i].cap[0] + (c->host_inst[i].nsp > 1 ? c->host_inst[i].cap[1] : 0);
+  c->inline_drain = slots_total <= kInlineDrainMaxSlots;
   drop_graphs(c);
 }
 
@@ -675,12 +680,22 @@ static pic_status enqueue_step(pic_ctx *c, hipStream_t st, bool sort, bool timed
   }
   if (all) { pic_status r = ev_end(c); if (r) return r; }
   if (pass) { pic_status r = ev_begin(c, 1); if (r) return r; }
-  HIP_TRY(c, launch_particles(c->d_inst, c->d_state, c->n_inst, c->prec, M_FUSED, c->tune.block,
-                              particle_grid(c, c->tune.block), c->max_n, st));
+  if (c->inline_drain) {
+    HIP_TRY(c, launch_particles(c->d_inst, c->d_state, c->n_inst, c->prec, M_FUSED_INLINE, 256,
+                                particle_grid(c, 256), c->max_n, st));
+  } else {
+    HIP_TRY(c, launch_particles(c->d_inst, c->d_state, c->n_inst, c->prec, M_FUSED, c->tune.block,
+                                particle_grid(c, c->tune.block), c->max_n, st));
+  }
   if (pass) { pic_status r = ev_end(c); if (r) return r; }
   if (all) { pic_status r = ev_begin(c, 3); if (r) return r; }
-  HIP_TRY(c, launch_drain(c->d_inst, c->d_state, c->n_inst, c->prec, M_FUSED, drain_grid(c, M_FUSED),
-                          !leave_open, st));
+  if (c->inline_drain) {
+    if (!leave_open) launch_finalize(c->d_inst, c->d_state, c->n_inst, st);
+    HIP_TRY(c, hipGetLastError());
+  } else {
+    HIP_TRY(c, launch_drain(c->d_inst, c->d_state, c->n_inst, c->prec, M_FUSED, drain_grid(c, M_FUSED),
+                            !leave_open, st));
+  }
   if (all) { pic_status r = ev_end(c); if (r) return r; }
   if (sort) {
     if (timed) { pic_status r = ev_begin(c, 2); if (r) return r; }

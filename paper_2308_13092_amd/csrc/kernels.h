@@ -7,6 +7,12 @@
 namespace ecpic {
 
 enum Mode : int { M_DEPOSIT = 0, M_PUSH = 1, M_MCC = 2, M_FUSED = 3, M_PULLBACK = 4 };
+// launch_particles only: the fused pass whose wavefronts drain their own
+// queued particles (256-thread workgroups; no k_drain launch follows).
+constexpr int M_FUSED_INLINE = 8;
+// Discharges of at most this many particle slots in all take the inline
+// drain: their steps are bound by launch latency, not by HBM.
+constexpr int64_t kInlineDrainMaxSlots = 4 << 20;
 
 // Particles per thread of a particle-kernel tile (a tile is block x this),
 // and the tile of the drain and of the sort scatter, in particles or entries.
@@ -37,6 +43,8 @@ hipError_t launch_drain(const InstDev *insts, InstState *states, int n_inst, int
 // Drain workgroups (of kDrainTile threads) resident on one CU at once, for the
 // given state form and pass mode (M_PUSH, M_MCC or M_FUSED).
 int drain_blocks_per_cu(int prec, int mode);
+// The closing kernel of a fused pass alone (after an inline-drained pass).
+void launch_finalize(const InstDev *insts, InstState *states, int n_inst, hipStream_t s);
 hipError_t launch_sort(const InstDev *insts, InstState *states, int n_inst, int prec, int grid,
                        int max_n, hipStream_t s);
 void launch_diag(const InstDev *insts, InstState *states, int inst, int prec, int64_t max_particles,
