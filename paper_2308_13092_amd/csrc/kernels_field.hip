@@ -164,6 +164,33 @@ k_field(const InstDev *__restrict__ insts, InstState *__restrict__ states, int m
   InstState &S = states[blockIdx.x];
   if ((I.N <= kFieldSmallCells) != (kFB == 256)) return;   // the other launch's instance
   const int t = threadIdx.x;
+  // The thread's nodes n = t + u kFB: both parities' deposits (the parity of
+  // step k is known only after the close below), h and V, loaded first so
+  // that their latency overlaps the close.  The deposits are final: the
+  // close does not touch them.  An empty slot (not active) has no arrays:
+  // nothing is loaded for it (it returns below).
+  constexpr int kNPT = ((kFB == 256 ? kFieldSmallCells : kMaxCells) + kFB) / kFB;
+  const int Nn = I.active ? I.N : -1;
+  const int nsp0 = I.nsp;
+  int64_t pa[2][2][kNPT];
+  double ph[kNPT], pv[kNPT];
+#pragma unroll
+  for (int u = 0; u < kNPT; ++u) {
+    const int n = t + u * kFB;
+    pa[0][0][u] = pa[0][1][u] = pa[1][0][u] = pa[1][1][u] = 0;
+    ph[u] = 0.0;
+    pv[u] = 1.0;
+    if (n <= Nn) {
+      pa[0][0][u] = I.A[0][0][n];
+      pa[1][0][u] = I.A[1][0][n];
+      if (nsp0 > 1) {
+        pa[0][1][u] = I.A[0][1][n];
+        pa[1][1][u] = I.A[1][1][n];
+      }
+      if (n < Nn) ph[u] = I.h[n];
+      pv[u] = I.V[n];
+    }
+  }
   int64_t k;
   if (mode & 4) {
     // The first wavefront closes the previous step; k and whether the
@@ -191,12 +218,15 @@ k_field(const InstDev *__restrict__ insts, InstState *__restrict__ states, int m
   // a barrier in between) Q_n = sum_s (q_s W A_{s,n}) 2^-32 and the integer
   // Gauss-law differences.
   const bool int_path = !periodic && I.int_path;
-  for (int n = t; n <= N; n += kFB) {
-    const int64_t a0 = I.A[par][0][n];
-    const int64_t a1 = (nsp > 1) ? I.A[par][1][n] : 0;
+#pragma unroll
+  for (int u = 0; u < kNPT; ++u) {
+    const int n = t + u * kFB;
+    if (n > N) break;
+    const int64_t a0 = par ? pa[1][0][u] : pa[0][0][u];
+    const int64_t a1 = (nsp > 1) ? (par ? pa[1][1][u] : pa[0][1][u]) : 0;
     sA[0][n] = a0;
     sA[1][n] = a1;
-    if (n < N) sH[n] = I.h[n];
+    if (n < N) sH[n] = ph[u];
     double q = (I.qW[0] * (double)a0) * 0x1p-32;
     if (nsp > 1) q = q + (I.qW[1] * (double)a1) * 0x1p-32;
     sQ[n] = q;
@@ -290,7 +320,11 @@ k_field(const InstDev *__restrict__ insts, InstState *__restrict__ states, int m
   double fe = 0.0;
   for (int j = t; j < N; j += kFB) fe += sH[j] * sE[j] * sE[j];
   double nm = 0.0;
-  for (int n = t; n <= N; n += kFB) nm = fmax(nm, ((double)sA[0][n] * I.W * 0x1p-32) / I.V[n]);
+#pragma unroll
+  for (int u = 0; u < kNPT; ++u) {
+    const int n = t + u * kFB;
+    if (n <= N) nm = fmax(nm, ((double)sA[0][n] * I.W * 0x1p-32) / pv[u]);
+  }
   block_sum_max<kFB>(fe, nm, tmpd, tmpm);
   if (t == 0) {
     S.field_energy = 0.5 * kEPS0 * fe;
