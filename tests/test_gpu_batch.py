@@ -168,6 +168,29 @@ def test_launch_shape_does_not_change_results(gpu, block, bpc, prec):
         assert_same_instance(a, i, b, i)
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("block", [256, 1024])
+def test_inline_drain_equals_the_drain_kernel(gpu, prec, block):
+    """Contexts of at most 4M particle slots drain collisions and absorptions
+    inside the fused particle kernel; larger ones launch k_drain.  The same
+    discharges, given capacities that push the context over that bound (and
+    so onto the drain kernel, with the tuned workgroup size), end bitwise
+    equal: states by id, counters, profiles, deposits and fields."""
+    cfgs = [c for c in mixed_configs(prec) if c["n_cells"] > 0][:4]
+    big = [dict(c, capacity=1_200_000) for c in cfgs]
+    note("inline drain vs drain kernel", prec, block, [c["n_per_species"] for c in cfgs])
+    a, b = Context()(cfgs), Context()(big)
+    b.set_tuning(block=block, sort_interval=10)
+    a.step(37)
+    b.step(37)
+    for i in range(len(cfgs)):
+        assert_same_instance(a, i, b, i)
+    d = [a.diagnostics(i) for i in range(len(cfgs))]
+    # the drained paths were exercised: collisions and absorption
+    assert sum(int(x["elastic"]) for x in d) > 0
+    assert sum(int(np.sum(x["absorbed"])) for x in d) > 0
+
+
 def test_autotuner_keeps_results_and_picks_a_valid_setting(gpu):
     from paper_2308_13092_amd.autotune import autotune
     cfgs = [c for c in mixed_configs(1, n_scale=0.5) if c["n_cells"] > 0][:3]
