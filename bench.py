@@ -269,9 +269,58 @@ def cpu_baseline(n_per_species=2_000_000, seconds=12.0, min_steps=3):
         steps += 1
     el = time.perf_counter() - t0
     return dict(value=ps / el, unit="particle-steps/s", cores=1, kind="oracle",
-                sample=(f"NumPy FP64 oracle, single thread: the large workload's grid, drive and "
-                        f"density with {n_per_species} e- + {n_per_species} Ar+ (weights scaled), "
-                        f"{steps} steps after the initial load ({el:.1f} s)"))
+                sample=(f"NumPy oracle (FP64 arithmetic, FP32-state contract), single thread: the large "
+                        f"workload's grid, drive and density with {n_per_species} e- + {n_per_species} Ar+ "
+                        f"(weights scaled), {steps} steps after the initial load ({el:.1f} s)"))
+
+
+def _oracle_rate(cfg, max_steps, seconds):
+    """Particle-steps/s of the oracle on one discharge, stepped up to
+    max_steps or until `seconds` have elapsed (at least 3 steps)."""
+    os.environ["OMP_NUM_THREADS"] = "1"
+    from oracle.sim import Sim
+    sim = Sim(cfg)
+    t0 = time.perf_counter()
+    ps = 0
+    steps = 0
+    while steps < max_steps and (steps < 3 or time.perf_counter() - t0 < seconds):
+        ps += sum(sp.n for sp in sim.sp)
+        sim.step()
+        steps += 1
+    el = time.perf_counter() - t0
+    return dict(value=ps / el, steps=steps, seconds=round(el, 2))
+
+
+def _sweep_member(i, seconds):
+    from paper_2308_13092_amd import configs
+    return _oracle_rate(configs.sweep(256)[i], 2000, seconds)
+
+
+def cpu_baseline_workloads(seconds=5.0, workers=8, members=8):
+    """The oracle on the other workloads (host cores of this machine): the
+    small discharge (EC and MC, FP64) and the resolved one (FP32 state) on
+    one core each, and the batched sweep as a pool of `workers` processes
+    over its first `members` discharges (its aggregate is the sum of the
+    concurrent members' rates)."""
+    import multiprocessing
+    from concurrent.futures import ProcessPoolExecutor
+    from paper_2308_13092_amd import configs
+    out = {}
+    for g, name in ((0, "ec"), (1, "mc")):
+        r = _oracle_rate(configs.small(gather=g, precision=0), configs.SMALL_STEPS, seconds)
+        out[f"small_fp64_{name}"] = dict(r, unit="particle-steps/s", cores=1, kind="oracle")
+    r = _oracle_rate(configs.resolved(precision=1), configs.RESOLVED_STEPS, seconds)
+    out["resolved_512_fp32"] = dict(r, unit="particle-steps/s", cores=1, kind="oracle")
+    ctx = multiprocessing.get_context("spawn")
+    with ProcessPoolExecutor(max_workers=workers, mp_context=ctx) as ex:
+        rs = list(ex.map(_sweep_member, range(members), [seconds] * members))
+    out["sweep"] = dict(value=sum(r["value"] for r in rs), unit="particle-steps/s", cores=workers,
+                        kind="oracle", members=members,
+                        sample=f"the first {members} discharges of the sweep, one process each, "
+                               f"each stepped for about {seconds:g} s")
+    out["note"] = ("steps run up to the workload's own count or about %g s each; rates are per "
+                   "wall second on the stated cores" % seconds)
+    return out
 
 
 def main():
@@ -378,6 +427,7 @@ def main():
                                                     if isinstance(v, dict)), file=sys.stderr, flush=True)
 
     cpu = None if a.no_cpu else cpu_baseline()
+    cpu_more = None if a.no_cpu else cpu_baseline_workloads()
     line = {
         "metric": "particle-steps/sec at 1 MI355X, FP32-state vs FP64 plain; p50/p99 sweep latency",
         "value": r32["value"],
@@ -398,6 +448,7 @@ def main():
                    "tuning": r32["tuning"], "nu_max": r32["nu_max"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "cpu_baseline_workloads": cpu_more,
         "fp64_plain": fp64,
         "rebalanced": rebal,
         "batched_sweep": sweep,
