@@ -1762,9 +1762,11 @@ void launch_init(const InstDev *insts, InstState *states, int inst, int species,
 
 void launch_diag(const InstDev *insts, InstState *states, int inst, int prec, int64_t max_particles,
                  unsigned long long *out, hipStream_t s) {
-  // About 16 particles per thread, at most 256 blocks.
-  const int64_t b = (max_particles + 4095) / 4096;
-  const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(256, b)));
+  // About 32 particles per thread, at most 2048 blocks (8 per CU: enough
+  // loads in flight for a large instance; 256 blocks took 0.99 ms for 64 M
+  // particles), one atomic per block and quantity.
+  const int64_t b = (max_particles + 8191) / 8192;
+  const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(2048, b)));
   if (prec == 1)
     hipLaunchKernelGGL(k_diag<F32>, grid, dim3(256), 0, s, insts, states, inst, out);
   else
