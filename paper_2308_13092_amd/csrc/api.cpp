@@ -339,10 +339,10 @@ static int capped(const pic_ctx *c, int64_t grid, int64_t tile) {
 // the tuned value, or as many as fit in the CU's 160 KB of LDS at once (so
 // that every workgroup of the persistent grid is resident together), at most
 // 8; never more than the tiles the capacities hold.
-static int particle_grid(const pic_ctx *c, int block, bool sorted = false) {
+static int particle_grid(const pic_ctx *c, int block) {
   int per = c->tune.blocks_per_cu;
   if (per <= 0) {
-    const size_t lds = particle_lds_bytes(c->prec, c->max_n, c->tune.block, sorted) + 8192;
+    const size_t lds = particle_lds_bytes(c->prec, c->max_n, c->tune.block) + 8192;
     per = (int)std::min<size_t>(8, std::max<size_t>(1, (160 * 1024) / lds));
   }
   return capped(c, (int64_t)c->n_cu * per, (int64_t)block * kParticlesPerThread);
@@ -669,12 +669,8 @@ constexpr int64_t kFullTiming = 16;
 static pic_status enqueue_step(pic_ctx *c, hipStream_t st, bool sort, bool timed,
                                bool close_prev = false, bool leave_open = false) {
   const int64_t n_timed = timed ? c->timed_steps++ : 0;
-  // A sort step of the FP32 form (drained by k_drain) sorts inside its fused
-  // pass: the pass writes the sorted copy itself (k_particles, SORTED).
-  const bool fused_sort = sort && c->prec == PIC_FP32_STATE && !c->inline_drain;
   const bool all = timed && n_timed % kFullTiming == 0;
-  // the streaming kernel's timing samples regular steps only
-  const bool pass = timed && !fused_sort && n_timed % kPassTiming == 0;
+  const bool pass = timed && n_timed % kPassTiming == 0;
   if (all) { pic_status r = ev_begin(c, 0); if (r) return r; }
   launch_field(c->d_inst, c->d_state, c->n_inst, c->field_classes, close_prev ? 7 : 3, st);
   HIP_TRY(c, hipGetLastError());
@@ -684,15 +680,7 @@ static pic_status enqueue_step(pic_ctx *c, hipStream_t st, bool sort, bool timed
   }
   if (all) { pic_status r = ev_end(c); if (r) return r; }
   if (pass) { pic_status r = ev_begin(c, 1); if (r) return r; }
-  if (fused_sort) {
-    // timed as the step's sort: counts, ranges, the sorting pass, the switch
-    if (timed) { pic_status r = ev_begin(c, 2); if (r) return r; }
-    HIP_TRY(c, launch_sort_count_scan(c->d_inst, c->d_state, c->n_inst, c->prec, sort_grid(c), c->max_n, st));
-    HIP_TRY(c, launch_particles(c->d_inst, c->d_state, c->n_inst, c->prec, M_FUSED_SORT, c->tune.block,
-                                particle_grid(c, c->tune.block, true), c->max_n, st));
-    HIP_TRY(c, launch_sort_flip(c->d_inst, c->d_state, c->n_inst, st));
-    if (timed) { pic_status r = ev_end(c); if (r) return r; }
-  } else if (c->inline_drain) {
+  if (c->inline_drain) {
     HIP_TRY(c, launch_particles(c->d_inst, c->d_state, c->n_inst, c->prec, M_FUSED_INLINE, 256,
                                 particle_grid(c, 256), c->max_n, st));
   } else {
@@ -709,7 +697,7 @@ static pic_status enqueue_step(pic_ctx *c, hipStream_t st, bool sort, bool timed
                             !leave_open, st));
   }
   if (all) { pic_status r = ev_end(c); if (r) return r; }
-  if (sort && !fused_sort) {
+  if (sort) {
     if (timed) { pic_status r = ev_begin(c, 2); if (r) return r; }
     HIP_TRY(c, launch_sort(c->d_inst, c->d_state, c->n_inst, c->prec, sort_grid(c), c->max_n, st));
     if (timed) { pic_status r = ev_end(c); if (r) return r; }

@@ -406,25 +406,6 @@ __device__ inline void close_pass(CInst &I, InstState &S, int lane) {
   }
 }
 
-// Runs of equal keys in consecutive lanes of a wavefront (particles arrive
-// nearly sorted by cell, so a wavefront holds few runs).  Returns whether this
-// lane starts its run; len is the run's length and pos this lane's place in
-// it.  Letting only the first lane of a run update a counter avoids the
-// serialisation of many lanes updating one LDS address.
-__device__ __forceinline__ bool key_run(int key, int &len, int &pos) {
-  const int lane = __lane_id();
-  const int prev = __shfl_up(key, 1, 64);
-  const bool head = lane == 0 || key != prev;
-  const unsigned long long heads = __ballot(head);
-  const unsigned long long le = (2ull << lane) - 1ull;   // lanes 0..lane (all for lane 63)
-  const int h = 63 - __clzll((long long)(heads & le));
-  const unsigned long long above = heads & ~le;
-  const int nxt = above ? __ffsll((long long)above) - 1 : 64;
-  pos = lane - h;
-  len = nxt - h;
-  return head;
-}
-
 // ---------------------------------------------------------------------------
 // Persistent grids over concatenated segments (instance x species)
 // ---------------------------------------------------------------------------

@@ -10,10 +10,6 @@ enum Mode : int { M_DEPOSIT = 0, M_PUSH = 1, M_MCC = 2, M_FUSED = 3, M_PULLBACK 
 // launch_particles only: the fused pass whose wavefronts drain their own
 // queued particles (256-thread workgroups; no k_drain launch follows).
 constexpr int M_FUSED_INLINE = 8;
-// launch_particles only: the fused pass of a sort step (FP32 form), writing
-// the sorted copy itself (see k_particles); preceded by
-// launch_sort_count_scan and followed by launch_sort_flip.
-constexpr int M_FUSED_SORT = 9;
 // Discharges of at most this many particle slots in all take the inline
 // drain: their steps are bound by launch latency, not by HBM.
 constexpr int64_t kInlineDrainMaxSlots = 4 << 20;
@@ -25,7 +21,7 @@ constexpr int kDrainTile = 256;
 constexpr int kSortTile = 1024;
 
 // Dynamic LDS bytes of the particle kernels for grids of up to max_n cells.
-size_t particle_lds_bytes(int prec, int max_n, int block, bool sorted = false);
+size_t particle_lds_bytes(int prec, int max_n, int block);
 size_t sort_lds_bytes(int max_n, int prec);
 
 // Field solve of every instance; `classes` says which workgroup sizes the
@@ -51,12 +47,6 @@ int drain_blocks_per_cu(int prec, int mode);
 void launch_finalize(const InstDev *insts, InstState *states, int n_inst, hipStream_t s);
 hipError_t launch_sort(const InstDev *insts, InstState *states, int n_inst, int prec, int grid,
                        int max_n, hipStream_t s);
-// The first two passes of the sort alone (cell counts, cell ranges), and the
-// switch of buffers after a fused sort pass (extents become the sorted
-// counts) for the instances that pass advanced.
-hipError_t launch_sort_count_scan(const InstDev *insts, InstState *states, int n_inst, int prec, int grid,
-                                  int max_n, hipStream_t s);
-hipError_t launch_sort_flip(const InstDev *insts, InstState *states, int n_inst, hipStream_t s);
 void launch_diag(const InstDev *insts, InstState *states, int inst, int prec, int64_t max_particles,
                  unsigned long long *out, hipStream_t s);
 void launch_zero_deposit(const InstDev *insts, InstState *states, int n_inst, hipStream_t s);

@@ -637,17 +637,7 @@ __device__ void drain_one(CInst &I, InstState &S, Smem &sm, int sp, int buf, int
 // The collision code makes this variant large (about 275 VGPRs); it is held
 // to two wavefronts per SIMD (256 VGPRs, a few spills), which measured
 // faster than one (resolved discharge, FP64: 38.3 against 47.9 us/step).
-// SORTED (fused pass of the FP32 form on a step that ends with a cell sort):
-// the pass writes every particle straight to its slot in the other buffer,
-// ordered by the cell it starts the step in, instead of in place; the
-// separate scatter of the sorted copy is saved.  Before it, k_sort_count and
-// k_sort_scan have counted the step-start cells and placed each cell's
-// range; each workgroup counts its own piece of a segment again in LDS and
-// reserves its share of every cell's range with one atomic per cell (as the
-// scatter of kernels_sort.hip does).  Particles absorbed in the step keep
-// their slot, marked absorbed, until the next sort; queue records carry the
-// new slots, and k_sort_flip switches the buffers before the drain.
-template <class F, int MODE, int BLOCK, bool INLINE = false, bool SORTED = false>
+template <class F, int MODE, int BLOCK, bool INLINE = false>
 __global__ void __launch_bounds__(BLOCK, INLINE ? 2 : 1)
 k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, int n_inst, int max_n) {
   constexpr int TILE = BLOCK * kPPT;
@@ -670,11 +660,6 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
                                        : (size_t)np1 * 24 + 8;
   int4 *wq = reinterpret_cast<int4 *>(dsm + ((tables + 15) & ~(size_t)15)) + (t >> 6) * kWaveQ;
   int wq_n = 0;   // entries in this wavefront's queue (wavefront-uniform)
-  // SORTED: per-cell counts, then cursors (u32[max_n]), and the piece's base
-  // slot of every cell (u64[max_n]), after the wavefront queues.
-  unsigned char *sort_lds = dsm + ((tables + 15) & ~(size_t)15) + (size_t)(BLOCK / 64) * kWaveQ * sizeof(int4);
-  unsigned int *scnt = reinterpret_cast<unsigned int *>(sort_lds);
-  unsigned long long *sgb = reinterpret_cast<unsigned long long *>(sort_lds + (((size_t)max_n * 4 + 15) & ~(size_t)15));
 
   if (t < kNctr) sm.ctr[t] = 0;
   if (MODE == M_DEPOSIT || MODE == M_FUSED)
@@ -690,7 +675,6 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
   int sp = 0, N = 0;
   int64_t k = 0, ext = 0, seg_first = 0;
   typename F::View P;
-  typename F::View Pd;   // SORTED: the other buffer, which receives the sorted copy
   int64_t *A_out = nullptr;
   int4 *gq = nullptr;
   bool deposit_on = false;
@@ -773,11 +757,7 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
       k = uni((int64_t)Sp->k);
       ext = uni((int64_t)Sp->extent[sp]);
       seg_first = uni((int64_t)sm.seg_prefix[seg]);
-      {
-        const int par_s = uni(Sp->parity);
-        P = F::view(I, sp, par_s);
-        if constexpr (SORTED) Pd = F::view(I, sp, par_s ^ 1);
-      }
+      P = F::view(I, sp, Sp->parity);
       gq = I.queue[sp];
       const int par = (int)(k & 1);
       G = GridPar{uni(I.N), uni(I.bc == 1 ? 1 : 0), uni(I.uniform), uni(I.dx)};
@@ -823,43 +803,6 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
         }
       }
       __syncthreads();
-      if constexpr (SORTED) {
-        // The piece [tile, pe) of this segment: count its particles by
-        // step-start cell, then reserve its share of each cell's range.
-        CInst &I = *Ip;
-        const int64_t pe = min(t1, (int64_t)sm.seg_prefix[seg + 1]);
-        for (int j = t; j < N; j += BLOCK) scnt[j] = 0u;
-        __syncthreads();
-        for (int64_t tt = tile; tt < pe; ++tt) {
-          const int64_t j0 = (tt - seg_first) * TILE + (int64_t)t * kPPT;
-          uint32_t h[kPPT];
-          if (j0 + kPPT <= ext) {
-#pragma unroll
-            for (int g = 0; g < kPPT; g += 4) {
-              const int4 h4 = gload4(reinterpret_cast<const int *>(P.hw) + j0 + g);
-              h[g] = (uint32_t)h4.x; h[g + 1] = (uint32_t)h4.y; h[g + 2] = (uint32_t)h4.z; h[g + 3] = (uint32_t)h4.w;
-            }
-          } else {
-#pragma unroll
-            for (int q = 0; q < kPPT; ++q) h[q] = (j0 + q < ext) ? gload<uint32_t>(P.hw + j0 + q) : kHwDead;
-          }
-#pragma unroll
-          for (int q = 0; q < kPPT; ++q) {
-            const int key = (hw_live(h[q]) && hw_cell(h[q]) < N) ? hw_cell(h[q]) : -1;
-            int len, pos;
-            if (key_run(key, len, pos) && key >= 0) atomicAdd(&scnt[key], (unsigned int)len);
-          }
-        }
-        __syncthreads();
-        for (int j = t; j < N; j += BLOCK) {
-          const unsigned int c = scnt[j];
-          if (c) {
-            sgb[j] = atomicAdd(&I.scursor[sp][j], (unsigned long long)c);
-            scnt[j] = 0u;
-          }
-        }
-        __syncthreads();
-      }
     }
     CInst &I = *Ip;
     const int64_t base = (tile - seg_first) * TILE;
@@ -1018,30 +961,7 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
       }
       }
       if constexpr (MODE == M_DEPOSIT || MODE == M_FUSED) dep.flush(sA);
-      if constexpr (SORTED) {
-        // Each particle that started the step live goes to the next slot of
-        // its step-start cell in the other buffer, with its cold record (and
-        // its knext entry when far); one LDS cursor atomic per run of equal
-        // cells across the wavefront.
-#pragma unroll
-        for (int q = 0; q < kPPT; ++q) {
-          const int key = (hw_live(hw[q]) && hw_cell(hw[q]) < N) ? hw_cell(hw[q]) : -1;
-          int len, pos;
-          unsigned int b0 = 0u;
-          if (key_run(key, len, pos) && key >= 0) b0 = atomicAdd(&scnt[key], (unsigned int)len);
-          b0 = __shfl(b0, lane - pos, 64);
-          if (key >= 0) {
-            const int64_t d = (int64_t)(sgb[key] + b0 + (unsigned int)pos);
-            const int64_t ii = i0 + q;
-            gstore<uint32_t>(Pd.hw + d, hn[q]);
-            gstore<float>(Pd.off + d, on[q]);
-            gstore<float>(Pd.vx + d, vn[q]);
-            gstore_cold(Pd.cold + d, gload_cold(P.cold + ii));
-            if (hw_far(hn[q])) gstore<int>(Pd.knext + d, P.knext[ii]);
-            went[q] = (went[q] & ~kQMask) | (int)d;
-          }
-        }
-      } else if constexpr (MODE == M_PUSH || MODE == M_FUSED || MODE == M_PULLBACK || MODE == M_MCC) {
+      if constexpr (MODE == M_PUSH || MODE == M_FUSED || MODE == M_PULLBACK || MODE == M_MCC) {
         if (full) {
 #pragma unroll
           for (int g = 0; g < kPPT; g += 4) {
@@ -1738,22 +1658,21 @@ __global__ void k_zero_deposit(const InstDev *__restrict__ insts, const InstStat
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-size_t particle_lds_bytes(int prec, int max_n, int block, bool sorted) {
+size_t particle_lds_bytes(int prec, int max_n, int block) {
   const size_t np1 = (size_t)max_n + 1;
   const size_t tables =
       (prec == 1) ? ((np1 * 8 + 15) & ~(size_t)15) + (size_t)max_n * 16 + (np1 + 1) * 4
                   : np1 * 24 + 8;
   const size_t q = (size_t)(block / 64) * kWaveQ * sizeof(int4);
-  const size_t srt = sorted ? (((size_t)max_n * 4 + 15) & ~(size_t)15) + (size_t)max_n * 8 : 0;
-  return ((tables + 15) & ~(size_t)15) + q + srt;
+  return ((tables + 15) & ~(size_t)15) + q;
 }
 
-template <class F, int MODE, int BLOCK, bool INLINE = false, bool SORTED = false>
+template <class F, int MODE, int BLOCK, bool INLINE = false>
 static hipError_t launch_pk(const InstDev *insts, InstState *states, int n_inst, int grid,
                             int max_n, hipStream_t s) {
-  const size_t lds = particle_lds_bytes(F::prec, max_n, BLOCK, SORTED);
-  hipLaunchKernelGGL((k_particles<F, MODE, BLOCK, INLINE, SORTED>), dim3(grid), dim3(BLOCK), lds, s, insts,
-                     states, n_inst, max_n);
+  const size_t lds = particle_lds_bytes(F::prec, max_n, BLOCK);
+  hipLaunchKernelGGL((k_particles<F, MODE, BLOCK, INLINE>), dim3(grid), dim3(BLOCK), lds, s, insts, states,
+                     n_inst, max_n);
   return hipGetLastError();
 }
 
@@ -1811,15 +1730,6 @@ template <class F>
 static hipError_t launch_form(const InstDev *insts, InstState *states, int n_inst, int mode,
                               int block, int grid, int max_n, hipStream_t s) {
   if (mode == M_FUSED_INLINE) return launch_pk<F, M_FUSED, 256, true>(insts, states, n_inst, grid, max_n, s);
-  if (mode == M_FUSED_SORT) {
-    if constexpr (F::prec == 1) {
-      if (block == 256) return launch_pk<F, M_FUSED, 256, false, true>(insts, states, n_inst, grid, max_n, s);
-      if (block == 512) return launch_pk<F, M_FUSED, 512, false, true>(insts, states, n_inst, grid, max_n, s);
-      return launch_pk<F, M_FUSED, 1024, false, true>(insts, states, n_inst, grid, max_n, s);
-    } else {
-      return hipErrorInvalidValue;
-    }
-  }
   if (mode == M_FUSED && block == 512)
     return launch_pk<F, M_FUSED, 512>(insts, states, n_inst, grid, max_n, s);
   if (mode == M_FUSED && block == 1024)

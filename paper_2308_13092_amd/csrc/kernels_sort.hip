@@ -49,6 +49,25 @@ __device__ __forceinline__ int key_of(CInst &I, const P64 &P, int64_t i, const d
   return lo;
 }
 
+// Runs of equal keys in consecutive lanes of a wavefront (particles arrive
+// nearly sorted by cell, so a wavefront holds few runs).  Returns whether this
+// lane starts its run; len is the run's length and pos this lane's place in
+// it.  Letting only the first lane of a run update a counter avoids the
+// serialisation of many lanes updating one LDS address.
+__device__ __forceinline__ bool key_run(int key, int &len, int &pos) {
+  const int lane = __lane_id();
+  const int prev = __shfl_up(key, 1, 64);
+  const bool head = lane == 0 || key != prev;
+  const unsigned long long heads = __ballot(head);
+  const unsigned long long le = (2ull << lane) - 1ull;   // lanes 0..lane (all for lane 63)
+  const int h = 63 - __clzll((long long)(heads & le));
+  const unsigned long long above = heads & ~le;
+  const int nxt = above ? __ffsll((long long)above) - 1 : 64;
+  pos = lane - h;
+  len = nxt - h;
+  return head;
+}
+
 // Segment tile prefix over the instances that are not frozen.
 __device__ void seg_prefix_setup(const InstDev *insts, const InstState *states, int n_inst,
                                  int *prefix, int tile = kSTile) {
@@ -412,40 +431,8 @@ k_sort_finish(const InstDev *__restrict__ insts, InstState *__restrict__ states,
   }
 }
 
-// After a fused sort pass (k_particles, SORTED): the instances it advanced
-// take the sorted buffer, whose extent is the count of their particles that
-// started the step live (absorbed ones hold marked slots until the next
-// sort).  Instances the pass skipped (frozen, or at their last step) keep
-// their buffer.
-__global__ void __launch_bounds__(256)
-k_sort_flip(const InstDev *__restrict__ insts, InstState *__restrict__ states, int n_inst) {
-  for (int i = threadIdx.x; i < n_inst; i += blockDim.x) {
-    CInst &I = cinst(insts)[i];
-    InstState &S = states[i];
-    if (!pass_open(I, S)) continue;
-    for (int s = 0; s < I.nsp; ++s) S.extent[s] = S.sort_live[s];
-    S.parity ^= 1;
-  }
-}
-
 size_t sort_lds_bytes(int max_n, int prec) {
   return 4 * (size_t)((max_n + 2) & ~1) + 8 * (size_t)max_n + (prec == 0 ? 8 * (size_t)(max_n + 1) : 0);
-}
-
-hipError_t launch_sort_count_scan(const InstDev *insts, InstState *states, int n_inst, int prec, int grid,
-                                  int max_n, hipStream_t s) {
-  const size_t lds_count = 4 * (size_t)((max_n + 2) & ~1) + (prec == 0 ? 8 * (size_t)(max_n + 1) : 0);
-  if (prec == 1)
-    hipLaunchKernelGGL(k_sort_count<P32>, dim3(grid), dim3(kSB), lds_count, s, insts, states, n_inst, max_n);
-  else
-    hipLaunchKernelGGL(k_sort_count<P64>, dim3(grid), dim3(kSB), lds_count, s, insts, states, n_inst, max_n);
-  hipLaunchKernelGGL(k_sort_scan, dim3(n_inst), dim3(kSB), 0, s, insts, states);
-  return hipGetLastError();
-}
-
-hipError_t launch_sort_flip(const InstDev *insts, InstState *states, int n_inst, hipStream_t s) {
-  hipLaunchKernelGGL(k_sort_flip, dim3(1), dim3(256), 0, s, insts, states, n_inst);
-  return hipGetLastError();
 }
 
 hipError_t launch_sort(const InstDev *insts, InstState *states, int n_inst, int prec, int grid,
