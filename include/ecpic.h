@@ -126,7 +126,8 @@ typedef struct pic_config {
      deposit and weighted sums are in units of W/16.  See pic_rebalance. */
   int32_t rebalance_ppc;
   int32_t rebalance_every;  /* pic_step rebalances every this many steps (context-wide:
-                               the value of the first active instance); 0 = never  */
+                               the value of the first instance that sets it, at
+                               pic_init or pic_slot_reset); 0 = never              */
   double rebalance_dv_e;    /* velocity-bin width of merges (m/s); 0 -> sqrt(e te / m_e) / 4 */
   double rebalance_dv_i;    /* the same for ions; 0 -> sqrt(e ti / M) / 4                 */
 } pic_config;

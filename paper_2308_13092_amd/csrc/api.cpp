@@ -1564,6 +1564,8 @@ pic_status pic_slot_reset(pic_ctx *c, int32_t inst, const pic_config *cfg) {
   r = deposit_only(c, inst);
   if (r != PIC_OK) return r;
   if (c->tune.sort_interval == 0 && cfg->sort_interval > 0) c->tune.sort_interval = cfg->sort_interval;
+  if (c->rebalance_every == 0 && cfg->rebalance_ppc > 0 && cfg->rebalance_every > 0)
+    c->rebalance_every = cfg->rebalance_every;
   return PIC_OK;
 }
 
