@@ -173,3 +173,23 @@ def test_run_with_rebalancing_every_10_steps(gpu):
         # charge: the deposit holds every particle's weight exactly (units W/16 x 2^-32)
         g = ctx.get_state(0, s)
         assert d["deposit_total"][s] == int((np.int64(1) << g["wc"].astype(np.int64)).sum()) * 2 ** 32
+
+
+def test_rebalancing_of_a_served_slot(gpu):
+    """A discharge admitted into an empty slot (as the server does) with a
+    rebalancing cadence: pic_step rebalances it at that cadence, and it ends
+    as the same discharge in a context of its own."""
+    from paper_2308_13092_amd import Context
+    from paper_2308_13092_amd.configs import base
+    cfg = rb_cfg(n=20_000, ppc=150, rebalance_every=6, sort_interval=5)
+    note("served slot rebalancing", cfg["n_per_species"])
+    served = Context([base(n_cells=0, precision=1)] * 3)
+    served.slot_reset(1, cfg)
+    alone = Context([cfg])
+    served.step(13)
+    alone.step(13)
+    ds, da = served.diagnostics(1), alone.diagnostics(0)
+    assert int(ds["merges"][0]) > 0 and list(ds["merges"]) == list(da["merges"])
+    assert list(ds["splits"]) == list(da["splits"])
+    for s in range(2):
+        same_by_id(served.get_state(1, s), alone.get_state(0, s), keys=("cell", "off", "vx", "vy", "vz", "wc", "knext"))
