@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define PIC_ABI_VERSION 6
+#define PIC_ABI_VERSION 7
 
 typedef struct pic_ctx pic_ctx;  /* opaque; owns host-side metadata only */
 
@@ -196,6 +196,12 @@ typedef struct pic_tuning {
   int32_t sort_interval;  /* steps between cell sorts (0 = never)                     */
   int32_t use_graph;      /* 1 = replay pic_step through captured HIP graphs; 0 = plain
                              launches (default: measured faster here)                */
+  int32_t inline_drain;   /* where the fused pass's queued particles are drained: 0 =
+                             chosen by size (default): in the particle kernel itself
+                             when the context's discharges start with at most 4 M
+                             particles in all (their steps are launch-bound), else
+                             by a drain kernel; 1 = always inline; 2 = never.  The
+                             results are the same either way.                        */
 } pic_tuning;
 
 /* Kernel timing (pic_kernel_times).  Durations in milliseconds summed over the

@@ -66,7 +66,7 @@ class pic_state_view(C.Structure):
 
 class pic_tuning(C.Structure):
     _fields_ = [("block", C.c_int32), ("blocks_per_cu", C.c_int32), ("sort_interval", C.c_int32),
-                ("use_graph", C.c_int32)]
+                ("use_graph", C.c_int32), ("inline_drain", C.c_int32)]
 
 
 class pic_kernel_time(C.Structure):
@@ -223,7 +223,10 @@ class Context:
             msg = self.lib.pic_last_error(None)
             raise PicError(st, "pic_init: " + (msg.decode() if msg else ""))
         self.n_inst = len(cfgs)
-        self.prec = next((int(c.get("precision", 0)) for c in cfgs if c.get("n_cells", 0)), 0)
+        # the library's rule: the first discharge's form, else (all slots
+        # empty) the first entry's
+        first = int(cfgs[0].get("precision", 0)) if cfgs else 0
+        self.prec = next((int(c.get("precision", 0)) for c in cfgs if c.get("n_cells", 0)), first)
 
     # -- plumbing -----------------------------------------------------------
     def _check(self, st, what, allow=()):
@@ -444,7 +447,7 @@ class Context:
         t = pic_tuning()
         self._check(self.lib.pic_get_tuning(self.ctx, C.byref(t)), "pic_get_tuning")
         return dict(block=t.block, blocks_per_cu=t.blocks_per_cu, sort_interval=t.sort_interval,
-                    use_graph=t.use_graph)
+                    use_graph=t.use_graph, inline_drain=t.inline_drain)
 
     def set_tuning(self, **kw):
         cur = self.tuning()

@@ -258,7 +258,7 @@ struct pic_ctx {
   // 1024 threads per block: measured fastest on the large workload.  Plain
   // launches: on every workload measured they beat graph replay (by about
   // 10 % on the small and resolved discharges, 1 % on the large one).
-  pic_tuning tune{1024, 0, 0, 0};
+  pic_tuning tune{1024, 0, 0, 0, 0};
   int rebalance_every = 0;     // pic_step rebalances every this many steps (0 = never)
   int64_t host_step = 0;
   bool deposit_current = false;
@@ -300,6 +300,16 @@ static void drop_graphs(pic_ctx *c) {
   c->graph_max_n = -1;
 }
 
+// Where the fused pass's queued particles are drained (pic_tuning.inline_drain):
+// by default inline when the discharges start with at most
+// kInlineDrainMaxSlots particles in all.
+static void choose_drain(pic_ctx *c) {
+  int64_t total = 0;
+  for (int i = 0; i < c->n_inst && i < (int)c->host_inst.size(); ++i)
+    if (c->slots[i].used) total += c->host_inst[i].n_init[0] + (c->host_inst[i].nsp > 1 ? c->host_inst[i].n_init[1] : 0);
+  c->inline_drain = c->tune.inline_drain == 1 || (c->tune.inline_drain == 0 && total <= kInlineDrainMaxSlots);
+}
+
 // Called whenever the set of slots changes: the grid bound and the grid
 // sizes (which follow the slots' capacities) change with it, so the captured
 // graphs are dropped.
@@ -312,10 +322,7 @@ static void recompute_max_n(pic_ctx *c) {
       c->field_classes |= field_class((int)s.cfg.n_cells);
     }
   c->max_n = (m + 3) / 4 * 4;
-  int64_t slots_total = 0;
-  for (int i = 0; i < c->n_inst && i < (int)c->host_inst.size(); ++i)
-    if (c->slots[i].used) slots_total += c->host_inst[i].cap[0] + (c->host_inst[i].nsp > 1 ? c->host_inst[i].cap[1] : 0);
-  c->inline_drain = slots_total <= kInlineDrainMaxSlots;
+  choose_drain(c);
   drop_graphs(c);
 }
 
@@ -1597,7 +1604,9 @@ pic_status pic_set_tuning(pic_ctx *c, const pic_tuning *t) {
   if (t->blocks_per_cu < 0 || t->blocks_per_cu > 16)
     return fail(c, PIC_EINVAL, "blocks_per_cu in [0, 16] (0 = as many as fit)");
   if (t->sort_interval < 0) return fail(c, PIC_EINVAL, "sort_interval must be >= 0");
+  if (t->inline_drain < 0 || t->inline_drain > 2) return fail(c, PIC_EINVAL, "inline_drain must be 0, 1 or 2");
   c->tune = *t;
+  choose_drain(c);
   drop_graphs(c);
   return PIC_OK;
 }

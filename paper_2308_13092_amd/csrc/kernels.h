@@ -10,8 +10,9 @@ enum Mode : int { M_DEPOSIT = 0, M_PUSH = 1, M_MCC = 2, M_FUSED = 3, M_PULLBACK 
 // launch_particles only: the fused pass whose wavefronts drain their own
 // queued particles (256-thread workgroups; no k_drain launch follows).
 constexpr int M_FUSED_INLINE = 8;
-// Discharges of at most this many particle slots in all take the inline
-// drain: their steps are bound by launch latency, not by HBM.
+// Contexts whose discharges start with at most this many particles in all
+// take the inline drain by default: their steps are bound by launch
+// latency, not by HBM.
 constexpr int64_t kInlineDrainMaxSlots = 4 << 20;
 
 // Particles per thread of a particle-kernel tile (a tile is block x this),

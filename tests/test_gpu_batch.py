@@ -171,16 +171,15 @@ def test_launch_shape_does_not_change_results(gpu, block, bpc, prec):
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("block", [256, 1024])
 def test_inline_drain_equals_the_drain_kernel(gpu, prec, block):
-    """Contexts of at most 4M particle slots drain collisions and absorptions
-    inside the fused particle kernel; larger ones launch k_drain.  The same
-    discharges, given capacities that push the context over that bound (and
-    so onto the drain kernel, with the tuned workgroup size), end bitwise
-    equal: states by id, counters, profiles, deposits and fields."""
+    """Small contexts drain collisions and absorptions inside the fused
+    particle kernel (pic_tuning.inline_drain = 0 chooses it by size, 1 forces
+    it); with 2 they launch k_drain.  The same discharges end bitwise equal
+    either way: states by id, counters, profiles, deposits and fields."""
     cfgs = [c for c in mixed_configs(prec) if c["n_cells"] > 0][:4]
-    big = [dict(c, capacity=1_200_000) for c in cfgs]
     note("inline drain vs drain kernel", prec, block, [c["n_per_species"] for c in cfgs])
-    a, b = Context()(cfgs), Context()(big)
-    b.set_tuning(block=block, sort_interval=10)
+    a, b = Context()(cfgs), Context()(cfgs)
+    assert a.tuning()["inline_drain"] == 0
+    b.set_tuning(block=block, inline_drain=2)
     a.step(37)
     b.step(37)
     for i in range(len(cfgs)):

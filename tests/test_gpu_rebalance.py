@@ -180,11 +180,12 @@ def test_rebalancing_of_a_served_slot(gpu):
     rebalancing cadence: pic_step rebalances it at that cadence, and it ends
     as the same discharge in a context of its own."""
     from paper_2308_13092_amd import Context
+    from paper_2308_13092_amd._lib import PIC_OK, slot_bytes
     from paper_2308_13092_amd.configs import base
     cfg = rb_cfg(n=20_000, ppc=150, rebalance_every=6, sort_interval=5)
     note("served slot rebalancing", cfg["n_per_species"])
-    served = Context([base(n_cells=0, precision=1)] * 3)
-    served.slot_reset(1, cfg)
+    served = Context([base(n_cells=0, precision=1)] * 3, pool_bytes=slot_bytes(cfg))
+    assert served.slot_reset(1, cfg) == PIC_OK
     alone = Context([cfg])
     served.step(13)
     alone.step(13)

@@ -35,7 +35,7 @@ def test_binding_covers_the_header():
 
 
 def test_abi_version_and_status_strings(lib):
-    assert lib.pic_abi_version() == 6
+    assert lib.pic_abi_version() == 7
     assert lib.pic_status_string(0) == b"ok"
 
 
