@@ -261,6 +261,10 @@ struct pic_ctx {
   pic_tuning tune{1024, 0, 0, 0, 0};
   int rebalance_every = 0;     // pic_step rebalances every this many steps (0 = never)
   int64_t host_step = 0;
+  // steps since the last sort of every slot (each sort moves the FP32 hot
+  // words' epoch to the current step; pic_step and pic_mcc force one before
+  // this reaches kRebaseSteps)
+  int64_t since_rebase = 0;
   bool deposit_current = false;
   std::string err;
   // graphs: [0] one step, [1] one step + sort
@@ -964,12 +968,14 @@ pic_status pic_mcc(pic_ctx *c) {
   HIP_TRY(c, launch_drain(c->d_inst, c->d_state, c->n_inst, c->prec, M_MCC, drain_grid(c, M_MCC), true, c->stream));
   c->deposit_current = false;
   c->host_step++;
+  if (++c->since_rebase >= kRebaseSteps) return pic_sort(c);
   return PIC_OK;
 }
 
 pic_status pic_sort(pic_ctx *c) {
   if (!c) return PIC_EINVAL;
   HIP_TRY(c, launch_sort(c->d_inst, c->d_state, c->n_inst, c->prec, sort_grid(c), c->max_n, c->stream));
+  c->since_rebase = 0;
   return PIC_OK;
 }
 
@@ -992,6 +998,7 @@ pic_status pic_rebalance(pic_ctx *c) {
   }
   // compact: the merged-away particles leave, the split children join the order
   HIP_TRY(c, launch_sort(c->d_inst, c->d_state, c->n_inst, c->prec, sort_grid(c), c->max_n, c->stream));
+  c->since_rebase = 0;
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->deposit_current = false;
   for (int i = 0; i < c->n_inst; ++i) {
@@ -1020,7 +1027,9 @@ pic_status pic_step(pic_ctx *c, int32_t n_steps) {
   bool open = false;
   const int R = c->rebalance_every;
   for (int n = 0; n < n_steps; ++n) {
-    const bool sort = S > 0 && ((c->host_step + 1) % S) == 0;
+    // a sort at its interval, or one that keeps the hot words' epoch offsets
+    // in range (see kRebaseSteps)
+    const bool sort = (S > 0 && ((c->host_step + 1) % S) == 0) || c->since_rebase + 1 >= kRebaseSteps;
     const bool rebal = R > 0 && ((c->host_step + 1) % R) == 0;
     if (c->timing || !c->tune.use_graph) {
       const bool leave_open = !sort && !rebal && n + 1 < n_steps;
@@ -1034,6 +1043,7 @@ pic_status pic_step(pic_ctx *c, int32_t n_steps) {
       HIP_TRY(c, hipGraphLaunch(g, c->stream));
     }
     c->host_step++;
+    c->since_rebase = sort ? 0 : c->since_rebase + 1;
     if (rebal) {
       pic_status r = pic_rebalance(c);
       if (r != PIC_OK) return r;
@@ -1144,7 +1154,7 @@ pic_status pic_get_state(pic_ctx *c, int32_t inst, int32_t species, pic_state_vi
       id[i] = cold[i].id;
       // the hot word's cell and candidacy (absolute step)
       cell[i] = hw_live(hw[i]) ? hw_cell(hw[i]) : -1;
-      if (hw_live(hw[i])) kn[i] = (int32_t)hw_knext(hw[i], kn[i], S.k);
+      if (hw_live(hw[i])) kn[i] = (int32_t)hw_knext(hw[i], kn[i], S.epoch);
     }
     for (int64_t i = 0; i < ext; ++i) live += cell[i] >= 0;
     if (live > v->n) { v->n = live; return fail(c, PIC_EINVAL, "view too small"); }
@@ -1228,7 +1238,7 @@ pic_status pic_set_state(pic_ctx *c, int32_t inst, int32_t species, const pic_st
       P32 P = view32(b, cap);
       std::vector<uint32_t> hw(n);
       for (int64_t i = 0; i < n; ++i)
-        hw[i] = hw_encode(v->cell[i], v->knext[i], S.k, v->wclass ? (int)v->wclass[i] : kClassUnit);
+        hw[i] = hw_encode(v->cell[i], v->knext[i], S.k, S.epoch, v->wclass ? (int)v->wclass[i] : kClassUnit);
       HIP_TRY(c, hipMemcpy(P.hw, hw.data(), 4 * n, hipMemcpyHostToDevice));
       HIP_TRY(c, hipMemcpy(P.off, v->off, 4 * n, hipMemcpyHostToDevice));
       HIP_TRY(c, hipMemcpy(P.vx, v->vx, 4 * n, hipMemcpyHostToDevice));
@@ -1262,13 +1272,15 @@ pic_status pic_set_step(pic_ctx *c, int32_t inst, int64_t k) {
   InstState S;
   r = read_state(c, inst, S);
   if (r != PIC_OK) return r;
-  if (c->prec == PIC_FP32_STATE && k != S.k) {
-    // the FP32 countdowns count from the step: re-express them
-    launch_reencode(c->d_inst, c->d_state, inst, S.k, k, c->stream);
+  if (c->prec == PIC_FP32_STATE) {
+    // the FP32 hot words: re-expressed for a next pass at step k, with
+    // epoch k
+    launch_reencode(c->d_inst, c->d_state, inst, S.epoch, k, c->stream);
     HIP_TRY(c, hipGetLastError());
     HIP_TRY(c, hipStreamSynchronize(c->stream));
   }
   S.k = k;
+  S.epoch = k;
   HIP_TRY(c, hipMemcpy(c->d_state + inst, &S, sizeof S, hipMemcpyHostToDevice));
   c->deposit_current = false;
   return PIC_OK;
@@ -1400,7 +1412,7 @@ struct CkptHeader {
   uint64_t total;
   CkptCfg cfg;
 };
-constexpr uint32_t kCkptVersion = 1;
+constexpr uint32_t kCkptVersion = 2;
 const char kCkptMagic[8] = {'E', 'C', 'P', 'I', 'C', 'C', 'K', '1'};
 
 CkptCfg ckpt_cfg(const pic_ctx *c, int inst) {
@@ -1545,7 +1557,16 @@ pic_status pic_checkpoint_load(pic_ctx *c, int32_t inst, const void *buf, size_t
     if (a.second) HIP_TRY(c, hipMemcpy(a.first, o, a.second, hipMemcpyHostToDevice));
     o += a.second;
   }
+  // the FP32 hot words: re-expressed from the current step (the context's
+  // sorts keep that epoch in range from here on)
+  const int64_t E0 = S.epoch;
+  S.epoch = S.k;
   HIP_TRY(c, hipMemcpy(c->d_state + inst, &S, sizeof S, hipMemcpyHostToDevice));
+  if (c->prec == PIC_FP32_STATE) {
+    launch_reencode(c->d_inst, c->d_state, inst, E0, S.k, c->stream);
+    HIP_TRY(c, hipGetLastError());
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
   c->deposit_current = false;   // the next step rebuilds the deposit of x^k (exact)
   return PIC_OK;
 }

@@ -11,10 +11,11 @@
 // aligned):
 //   FP32-state form: hw u32 | off f32 | vx f32 | knext i32 | {vy f32, vz f32, id u64}
 //   FP64 form:       x f64  | vx f64  | vy f64 | vz f64 | knext i32 | id u64
-// The FP32 form's hot word hw holds the cell and the steps left until the
-// particle's next collision candidacy (see hw_encode), so the streaming pass
-// reads 12 bytes per particle and writes 12; the fields it never reads sit in
-// one 16-B record per particle.
+// The FP32 form's hot word hw holds the cell and the particle's next collision
+// candidacy as an offset from the slot's epoch step (see hw_encode), so the
+// streaming pass reads 12 bytes per particle and writes at most 12 (the hot
+// word only when the cell or the candidacy changed); the fields it never
+// reads sit in one 16-B record per particle.
 // A dead (absorbed) particle keeps its slot until the next sort with
 // hw = kHwDead (FP32) or x = -1 (FP64).
 #pragma once
@@ -111,6 +112,9 @@ __device__ __forceinline__ CInst *cinst(const InstDev *p) { return (CInst *)p; }
 
 struct InstState {
   int64_t k;
+  // FP32 form: the step the hot words' candidacy offsets count from (set by
+  // every sort and re-encoding; k - epoch stays below kRebaseSteps + 1)
+  int64_t epoch;
   int32_t status, parity;
   int32_t frozen, pad0;
   int64_t extent[2];
@@ -135,19 +139,23 @@ struct InstState {
 // The FP32 form's hot word
 // ---------------------------------------------------------------------------
 // bits 0-11  cell (0xFFF: dead slot; grids have at most 2048 cells)
-// bits 12-27 countdown c: steps from the current step k to the particle's next
-//            collision candidacy, knext = k + c
+// bits 12-27 c: the particle's next collision candidacy knext as an offset
+//            from the slot's epoch E, knext = E + c
 // bits 28-30 weight class w: the particle's weight is W 2^(w-4) (4 unless
 //            the discharge is rebalanced)
-// bit  31    far: knext lies beyond the countdown's range (or before k); the
-//            knext array then holds it and c counts down towards a re-check
-// A candidate is a particle with c = 0 at its step (after a re-check of the
-// knext array when far).  Every pass that advances k decrements c, so the
-// countdown needs no read of the knext array.
+// bit  31    far: the knext array holds the candidacy (see hw_encode)
+// A particle is a candidate at the pass of step k when c == k - E, which
+// needs no read of the knext array and no change of the word from step to
+// step: a particle that keeps its cell keeps its word, and the streaming
+// pass does not store it.  Every sort re-expresses the offsets from the
+// step it runs before (E := k), and the host forces one at least every
+// kRebaseSteps steps, so k - E never reaches kCntMax.
 constexpr uint32_t kHwDead = 0xFFFFFFFFu;
 constexpr uint32_t kHwCell = 0xFFFu;
 constexpr int kHwShift = 12;
 constexpr uint32_t kCntMax = (1u << 16) - 1u;
+constexpr int64_t kRebaseSteps = 16384;
+static_assert(kRebaseSteps < (int64_t)kCntMax, "the epoch offset must stay below the far sentinel");
 constexpr int kHwClassShift = 28;
 constexpr uint32_t kHwClass = 7u << kHwClassShift;
 constexpr uint32_t kHwFar = 1u << 31;
@@ -158,22 +166,29 @@ __host__ __device__ inline uint32_t hw_cnt(uint32_t w) { return (w >> kHwShift) 
 __host__ __device__ inline bool hw_far(uint32_t w) { return (w & kHwFar) != 0u; }
 __host__ __device__ inline int hw_class(uint32_t w) { return (int)((w >> kHwClassShift) & 7u); }
 // The hot word of a particle of weight class cls in `cell` whose next
-// candidacy is step knext, seen from step k.
-__host__ __device__ inline uint32_t hw_encode(int cell, int64_t knext, int64_t k, int cls) {
+// candidacy is step knext, for a slot with epoch E whose next pass is step k
+// (E <= k < E + kCntMax):
+//   k <= knext < E + kCntMax  c = knext - E;
+//   knext < k (overdue)       far, c = k - E: a candidate at the next pass,
+//                             as a candidacy in the past is;
+//   knext >= E + kCntMax      far, c = kCntMax: never a candidate before the
+//                             next re-expression, which reads the knext array.
+__host__ __device__ inline uint32_t hw_encode(int cell, int64_t knext, int64_t k, int64_t E, int cls) {
   const uint32_t base = (uint32_t)cell | ((uint32_t)cls << kHwClassShift);
-  const int64_t w = knext - k;
-  if (w >= 0 && w <= (int64_t)kCntMax) return base | ((uint32_t)w << kHwShift);
-  return base | ((w < 0 ? 0u : kCntMax) << kHwShift) | kHwFar;
+  const int64_t w = knext - E;
+  if (knext >= k && w < (int64_t)kCntMax) return base | ((uint32_t)w << kHwShift);
+  const uint32_t c = knext < k ? (uint32_t)(k - E) : kCntMax;
+  return base | (c << kHwShift) | kHwFar;
 }
 // The particle's next candidacy (far_knext: its entry of the knext array).
-__host__ __device__ inline int64_t hw_knext(uint32_t w, int32_t far_knext, int64_t k) {
-  return hw_far(w) ? (int64_t)far_knext : k + (int64_t)hw_cnt(w);
+__host__ __device__ inline int64_t hw_knext(uint32_t w, int32_t far_knext, int64_t E) {
+  return hw_far(w) ? (int64_t)far_knext : E + (int64_t)hw_cnt(w);
 }
-// The same word in another cell, one step later (the countdown of a
-// particle that is not a candidate moves one step closer).
-__host__ __device__ inline uint32_t hw_advance(uint32_t w, int cell, bool count) {
-  const uint32_t dec = (count && hw_cnt(w) != 0u) ? (1u << kHwShift) : 0u;
-  return ((w & ~kHwCell) - dec) | (uint32_t)cell;
+// Whether the particle is a candidate at the pass of step k (kE = k - E).
+__host__ __device__ inline bool hw_due(uint32_t w, uint32_t kE) { return hw_cnt(w) == kE; }
+// The same word in another cell.
+__host__ __device__ inline uint32_t hw_move(uint32_t w, int cell) {
+  return (w & ~kHwCell) | (uint32_t)cell;
 }
 
 // ---------------------------------------------------------------------------
@@ -183,7 +198,7 @@ __host__ __device__ inline uint32_t hw_advance(uint32_t w, int cell, bool count)
 // arrays; the ones only collisions, emission, diagnostics and the sort touch
 // (vy, vz, id) form one 16-B record per particle, so that handling a single
 // particle costs one memory line for them instead of three.  knext is read
-// only for far particles (see hw_encode).
+// and written only for far particles (see hw_encode).
 struct Cold32 {
   float vy, vz;
   uint64_t id;

@@ -51,8 +51,9 @@ hipError_t launch_sort(const InstDev *insts, InstState *states, int n_inst, int 
 void launch_diag(const InstDev *insts, InstState *states, int inst, int prec, int64_t max_particles,
                  unsigned long long *out, hipStream_t s);
 void launch_zero_deposit(const InstDev *insts, InstState *states, int n_inst, hipStream_t s);
-// FP32 form: re-express instance inst's countdowns from step k1 (was k0).
-void launch_reencode(const InstDev *insts, InstState *states, int inst, int64_t k0, int64_t k1,
+// FP32 form: re-express instance inst's hot words, written with epoch E0,
+// for a next pass at step k1 with epoch k1 (the caller then sets both).
+void launch_reencode(const InstDev *insts, InstState *states, int inst, int64_t E0, int64_t k1,
                      hipStream_t s);
 // Velocity moments and power of the discharges whose averaging is due.
 void launch_moments(const InstDev *insts, InstState *states, int n_inst, int prec, int grid, int max_n,

@@ -503,13 +503,13 @@ struct F64 {
 
 // Write a new particle (SEE electron or ionisation product).
 // k1: the first step the particle takes part in; kn: its first candidacy;
-// cls: its weight class (FP32 form).
+// E: the slot's epoch; cls: its weight class (FP32 form).
 template <class F>
 __device__ void write_new(CInst &I, typename F::View P, int64_t idx, double x, int cell,
                          float off, double vx, double vy, double vz, uint64_t id, int32_t kn,
-                         int64_t k1, int cls) {
+                         int64_t k1, int64_t E, int cls) {
   if constexpr (F::prec == 1) {
-    const uint32_t w = hw_encode(cell, kn, k1, cls);
+    const uint32_t w = hw_encode(cell, kn, k1, E, cls);
     P.hw[idx] = w;
     P.off[idx] = off;
     P.vx[idx] = (float)vx;
@@ -529,7 +529,7 @@ __device__ void write_new(CInst &I, typename F::View P, int64_t idx, double x, i
 // electron goes straight into the electron deposit of step k+1 when `dep`.
 template <class F>
 __device__ void emit_secondary(CInst &I, InstState &S, Smem &sm, uint64_t ion_id, int wall,
-                               int64_t k, int buf, bool dep, int64_t *A_next_e, int cls) {
+                               int64_t k, int64_t E, int buf, bool dep, int64_t *A_next_e, int cls) {
   const uint4 r = philox((uint32_t)k, TAG_SEE | (1u << 8), I.seed, ion_id);
   if (!(u32d(r.x) < I.gamma_see)) return;
   const uint4 p = philox((uint32_t)k, TAG_SEE_POS | (1u << 8), I.seed, ion_id);
@@ -557,7 +557,7 @@ __device__ void emit_secondary(CInst &I, InstState &S, Smem &sm, uint64_t ion_id
   const int64_t idx = append_slot(I, S, 0);
   if (idx < 0) return;
   write_new<F>(I, F::view(I, 0, buf), idx, x, cell, off, vx, I.vt_see * zy, I.vt_see * zz, cid, kn, k + 1,
-               cls);
+               E, cls);
   atomicAdd(&sm.ctr[C_SEE], 1ull);
   if (dep) global_deposit(I, A_next_e, j, xi, weight_shift(cls, I.wunit));
 }
@@ -626,7 +626,7 @@ __device__ void flush_counters(Smem &sm, InstState *Sp, int sp) {
 }
 
 template <class F, int MODE>
-__device__ void drain_one(CInst &I, InstState &S, Smem &sm, int sp, int buf, int64_t k,
+__device__ void drain_one(CInst &I, InstState &S, Smem &sm, int sp, int buf, int64_t k, int64_t E,
                           typename F::View P, const int4 rec);
 
 // INLINE (fused pass, discharges small enough that launches dominate): each
@@ -673,7 +673,8 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
   CInst *Ip = nullptr;
   InstState *Sp = nullptr;
   int sp = 0, N = 0;
-  int64_t k = 0, ext = 0, seg_first = 0;
+  int64_t k = 0, epoch = 0, ext = 0, seg_first = 0;
+  uint32_t kE = 0;   // k - epoch: the hot-word offset of this pass's candidates
   typename F::View P;
   int64_t *A_out = nullptr;
   int4 *gq = nullptr;
@@ -705,7 +706,7 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
       // FP64 position, it reads with an L2 load).
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
       const int bufp = uni(Sp->parity);
-      for (int e = lane; e < n; e += 64) drain_one<F, MODE>(*Ip, *Sp, sm, sp, bufp, k, P, wq[wq_n - n + e]);
+      for (int e = lane; e < n; e += 64) drain_one<F, MODE>(*Ip, *Sp, sm, sp, bufp, k, epoch, P, wq[wq_n - n + e]);
       wq_n -= n;
       return;
     }
@@ -755,6 +756,8 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
       // every tile would wait at the loop's join for all outstanding memory
       // operations (the previous tile's stores included) before its loads.
       k = uni((int64_t)Sp->k);
+      epoch = uni((int64_t)Sp->epoch);
+      kE = (uint32_t)(k - epoch);
       ext = uni((int64_t)Sp->extent[sp]);
       seg_first = uni((int64_t)sm.seg_prefix[seg]);
       P = F::view(I, sp, Sp->parity);
@@ -815,7 +818,7 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
 
     if constexpr (F::prec == 1) {
       // ---------------- FP32-state form ----------------
-      // hw: hot word (cell, countdown to the next candidacy, far flag)
+      // hw: hot word (cell, candidacy offset from the epoch, class, far flag)
       uint32_t hw[kPPT];
       float o[kPPT], vx[kPPT];
       if (full) {
@@ -898,14 +901,14 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
           const int wall = st[q];
           const float v1 = vn[q];
           const bool gone = live && (wall != W_IN || v1 != v1);   // absorbed or non-finite
-          // a candidate this step: countdown at zero (the drain re-checks far ones)
-          const bool cand = MODE == M_FUSED && live && !gone && coll && hw_cnt(hw[q]) == 0u;
+          // a candidate this step (the drain re-checks far ones)
+          const bool cand = MODE == M_FUSED && live && !gone && coll && hw_due(hw[q], kE);
           live_here += live ? 1u : 0u;
           want[q] = gone || cand;
           went[q] = qentry(ii, gone ? ((wall == W_BAD || v1 != v1) ? 3 : (wall < 0 ? 1 : 2)) : 0);
-          // the countdown moves one step in the fused pass (the drain rewrites
-          // a candidate's word)
-          hn[q] = !live ? hw[q] : (gone ? kHwDead : hw_advance(hw[q], cn[q], MODE == M_FUSED && coll));
+          // the word changes with the cell only (the drain rewrites a
+          // candidate's word)
+          hn[q] = !live ? hw[q] : (gone ? kHwDead : hw_move(hw[q], cn[q]));
           on[q] = gone ? o[q] : on[q];
           if (live && !gone) {
             const int jj = cn[q];
@@ -954,9 +957,8 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
                                           : gather_ec2_32(sE32, j, o[q]);
           vn[q] = vx[q] - hq32 * e;
         } else if constexpr (MODE == M_MCC) {
-          want[q] = coll && hw_cnt(hw[q]) == 0u;
+          want[q] = coll && hw_due(hw[q], kE);
           went[q] = qentry(ii, 0);
-          hn[q] = hw_advance(hw[q], j, coll);
         }
       }
       }
@@ -965,9 +967,12 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
         if (full) {
 #pragma unroll
           for (int g = 0; g < kPPT; g += 4) {
+            // a hot word is stored only when one of the lane's four changed
+            // (a cell change, an absorption): most particles keep theirs
             if constexpr (MODE != M_PULLBACK)
-              gstore4(reinterpret_cast<int *>(P.hw) + i0 + g, (int)hn[g], (int)hn[g + 1], (int)hn[g + 2],
-                      (int)hn[g + 3]);
+              if (((hn[g] ^ hw[g]) | (hn[g + 1] ^ hw[g + 1]) | (hn[g + 2] ^ hw[g + 2]) | (hn[g + 3] ^ hw[g + 3])) != 0u)
+                gstore4(reinterpret_cast<int *>(P.hw) + i0 + g, (int)hn[g], (int)hn[g + 1], (int)hn[g + 2],
+                        (int)hn[g + 3]);
             if constexpr (MODE == M_PUSH || MODE == M_FUSED)
               gstore4(P.off + i0 + g, on[g], on[g + 1], on[g + 2], on[g + 3]);
             if constexpr (MODE != M_MCC) gstore4(P.vx + i0 + g, vn[g], vn[g + 1], vn[g + 2], vn[g + 3]);
@@ -977,7 +982,8 @@ k_particles(const InstDev *__restrict__ insts, InstState *__restrict__ states, i
           for (int q = 0; q < kPPT; ++q) {
             const int64_t i = i0 + q;
             if (i < ext) {
-              if constexpr (MODE != M_PULLBACK) gstore<uint32_t>(P.hw + i, hn[q]);
+              if constexpr (MODE != M_PULLBACK)
+                if (hn[q] != hw[q]) gstore<uint32_t>(P.hw + i, hn[q]);
               if constexpr (MODE == M_PUSH || MODE == M_FUSED) gstore<float>(P.off + i, on[q]);
               if constexpr (MODE != M_MCC) gstore<float>(P.vx + i, vn[q]);
             }
@@ -1175,7 +1181,7 @@ __device__ __forceinline__ void load_particle(const P64 &P, int64_t i, const int
 // null-collision candidate (collision, ionisation products, next candidate
 // step).  Products go straight into the deposit of step k+1 in the fused pass.
 template <class F, int MODE>
-__device__ void drain_one(CInst &I, InstState &S, Smem &sm, int sp, int buf, int64_t k,
+__device__ void drain_one(CInst &I, InstState &S, Smem &sm, int sp, int buf, int64_t k, int64_t E,
                           typename F::View P, const int4 rec) {
   const int entry = rec.x;
   const int64_t i = entry & kQMask;
@@ -1186,13 +1192,14 @@ __device__ void drain_one(CInst &I, InstState &S, Smem &sm, int sp, int buf, int
     return;
   }
   if constexpr (F::prec == 1) {
-    // A far particle whose countdown ran out before its candidacy: only its
-    // countdown is renewed (it is not a candidate).
+    // A far particle is queued only when its candidacy is overdue (see
+    // hw_encode); one whose knext entry says otherwise is re-expressed and
+    // is not a candidate.
     const uint32_t hw = (uint32_t)rec.y;
     if (kind == 0 && hw_far(hw)) {
       const int32_t kf = P.knext[i];
       if ((int64_t)kf > k) {
-        P.hw[i] = hw_encode(hw_cell(hw), kf, k + 1, hw_class(hw));
+        P.hw[i] = hw_encode(hw_cell(hw), kf, k + 1, E, hw_class(hw));
         return;
       }
     }
@@ -1211,7 +1218,7 @@ __device__ void drain_one(CInst &I, InstState &S, Smem &sm, int sp, int buf, int
     atomicAdd(&sm.ctr[C_EABS + 2 * sp + wi], (unsigned long long)rint(en * 65536.0) << sh);
     if (I.avg_every > 0 && k >= I.avg_start) record_impact(I, sp, wi, en, vxd, v2, 1ull << sh);
     if (sp == 1 && I.gamma_see > 0.0 && I.nsp > 1)
-      emit_secondary<F>(I, S, sm, id, wi == 0 ? -1 : 1, k, buf, MODE == M_FUSED,
+      emit_secondary<F>(I, S, sm, id, wi == 0 ? -1 : 1, k, E, buf, MODE == M_FUSED,
                         I.A[(k + 1) & 1][0], cls);
     return;
   }
@@ -1245,10 +1252,10 @@ __device__ void drain_one(CInst &I, InstState &S, Smem &sm, int sp, int buf, int
       // the pair carries the primary's weight
       if (ie >= 0)
         write_new<F>(I, P, ie, xx, cc, oo, ej[0], ej[1], ej[2], eid,
-                     next_candidate(eid, k, 0, I.seed, I.nudt[0]), k + 1, cls);
+                     next_candidate(eid, k, 0, I.seed, I.nudt[0]), k + 1, E, cls);
       if (ii >= 0)
         write_new<F>(I, F::view(I, 1, buf), ii, xx, cc, oo, gx, gy, gz, iid,
-                     next_candidate(iid, k, 1, I.seed, I.nudt[1]), k + 1, cls);
+                     next_candidate(iid, k, 1, I.seed, I.nudt[1]), k + 1, E, cls);
       if constexpr (MODE == M_FUSED) {
         int j;
         double xi;
@@ -1282,7 +1289,7 @@ __device__ void drain_one(CInst &I, InstState &S, Smem &sm, int sp, int buf, int
   }
   const int32_t kn = next_candidate(id, k, sp, I.seed, I.nudt[sp]);
   if constexpr (F::prec == 1) {
-    const uint32_t w = hw_encode(hw_cell((uint32_t)rec.y), kn, k + 1, cls);
+    const uint32_t w = hw_encode(hw_cell((uint32_t)rec.y), kn, k + 1, E, cls);
     P.hw[i] = w;
     if (hw_far(w)) P.knext[i] = kn;
   } else {
@@ -1306,7 +1313,7 @@ k_drain(const InstDev *__restrict__ insts, InstState *__restrict__ states, int n
   int seg = -1;
   InstState *Sp = nullptr;
   // per-segment values, in scalar registers
-  int64_t qn = 0, k = 0, first = 0;
+  int64_t qn = 0, k = 0, epoch = 0, first = 0;
   int buf = 0;
   for (int64_t tile = t0; tile < t1; ++tile) {
     int s = seg < 0 ? segment_of(sm.seg_prefix, 2 * n_inst, tile) : seg;
@@ -1318,13 +1325,15 @@ k_drain(const InstDev *__restrict__ insts, InstState *__restrict__ states, int n
       Sp = &states[seg >> 1];
       qn = uni((int64_t)Sp->qcount[seg & 1]);
       k = uni((int64_t)Sp->k);
+      epoch = uni((int64_t)Sp->epoch);
       buf = uni(Sp->parity);
       first = uni((int64_t)sm.seg_prefix[seg]);
     }
     CInst &I = cinst(insts)[seg >> 1];
     const int sp = seg & 1;
     const int64_t e = (tile - first) * BLOCK + t;
-    if (e < qn) drain_one<F, MODE>(I, *Sp, sm, sp, buf, k, F::view(I, sp, buf), gload_rec(I.queue[sp] + e));
+    if (e < qn)
+      drain_one<F, MODE>(I, *Sp, sm, sp, buf, k, epoch, F::view(I, sp, buf), gload_rec(I.queue[sp] + e));
   }
   if (seg >= 0) flush_counters<BLOCK>(sm, Sp, seg & 1);
 }
@@ -1370,7 +1379,7 @@ k_init(const InstDev *__restrict__ insts, InstState *__restrict__ states, int in
   int cell = 0;
   float off = 0.0f;
   if constexpr (F::prec == 1) to_state32(I, x, cell, off);
-  write_new<F>(I, P, i, x, cell, off, vx, vy, vz, id, kn, 0, kClassUnit);
+  write_new<F>(I, P, i, x, cell, off, vx, vy, vz, id, kn, states[inst].k, states[inst].epoch, kClassUnit);
 }
 
 // ---------------------------------------------------------------------------
@@ -1616,12 +1625,12 @@ k_moments(const InstDev *__restrict__ insts, const InstState *__restrict__ state
   if (seg >= 0) flush();
 }
 
-// The FP32 hot words of instance inst re-expressed from step k1 after its
-// step index changed from k0 (pic_set_step): the countdowns count from the
-// step, the candidacies they stand for stay where they are.
+// The FP32 hot words of instance inst, written with epoch E0, re-expressed
+// for a next pass at step k1 with epoch k1 (pic_set_step, a restored
+// checkpoint): the candidacies they stand for stay where they are.
 __global__ void __launch_bounds__(256)
 k_reencode(const InstDev *__restrict__ insts, const InstState *__restrict__ states, int inst,
-           int64_t k0, int64_t k1) {
+           int64_t E0, int64_t k1) {
   CInst &I = cinst(insts)[inst];
   const InstState &S = states[inst];
   for (int s = 0; s < I.nsp; ++s) {
@@ -1631,17 +1640,17 @@ k_reencode(const InstDev *__restrict__ insts, const InstState *__restrict__ stat
          i += (int64_t)gridDim.x * blockDim.x) {
       const uint32_t w = P.hw[i];
       if (!hw_live(w)) continue;
-      const int64_t kn = hw_knext(w, hw_far(w) ? P.knext[i] : 0, k0);
-      const uint32_t nw = hw_encode(hw_cell(w), kn, k1, hw_class(w));
+      const int64_t kn = hw_knext(w, hw_far(w) ? P.knext[i] : 0, E0);
+      const uint32_t nw = hw_encode(hw_cell(w), kn, k1, k1, hw_class(w));
       P.hw[i] = nw;
       if (hw_far(nw)) P.knext[i] = (int32_t)kn;
     }
   }
 }
 
-void launch_reencode(const InstDev *insts, InstState *states, int inst, int64_t k0, int64_t k1,
+void launch_reencode(const InstDev *insts, InstState *states, int inst, int64_t E0, int64_t k1,
                      hipStream_t s) {
-  hipLaunchKernelGGL(k_reencode, dim3(1024), dim3(256), 0, s, insts, states, inst, k0, k1);
+  hipLaunchKernelGGL(k_reencode, dim3(1024), dim3(256), 0, s, insts, states, inst, E0, k1);
 }
 
 __global__ void k_zero_deposit(const InstDev *__restrict__ insts, const InstState *__restrict__ states) {

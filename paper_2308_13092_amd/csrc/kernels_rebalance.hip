@@ -269,7 +269,7 @@ k_rb_split(const InstDev *__restrict__ insts, InstState *__restrict__ states, in
       const uint4 r = philox((uint32_t)k, TAG_SPLIT | (uint32_t)(s << 8), I.seed, c.id);
       const uint64_t cid = (uint64_t)r.x | ((uint64_t)r.y << 32);
       const int32_t kn = next_candidate(cid, k - 1, s, I.seed, I.nudt[s]);
-      const uint32_t cw = hw_encode(hw_cell(w), kn, k, cls);
+      const uint32_t cw = hw_encode(hw_cell(w), kn, k, S.epoch, cls);
       P.hw[at] = cw;
       P.off[at] = P.off[i];
       P.vx[at] = P.vx[i];

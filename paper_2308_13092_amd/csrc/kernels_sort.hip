@@ -303,6 +303,16 @@ __device__ __forceinline__ void store_rec(const P64 &P, int64_t d, const Rec64 &
   gstore<int>(P.knext + d, r.knext);
   gstore<uint64_t>(P.id + d, r.id);
 }
+// FP32 form: the hot word re-expressed from the slot's epoch E0 to the step k
+// of the next pass, which becomes the epoch (see hw_encode).  A far word
+// whose candidacy comes into range loses its knext entry; an overdue one
+// gains it.
+__device__ __forceinline__ void rebase_rec(Rec32 &r, int64_t E0, int64_t k) {
+  const int64_t kn = hw_knext(r.hw, r.knext, E0);
+  r.hw = hw_encode(hw_cell(r.hw), kn, k, k, hw_class(r.hw));
+  r.knext = (int)kn;
+}
+__device__ __forceinline__ void rebase_rec(Rec64 &, int64_t, int64_t) {}
 __device__ __forceinline__ int rec_key(CInst &I, const Rec32 &r, const double *) {
   return (hw_live(r.hw) && hw_cell(r.hw) < I.N) ? hw_cell(r.hw) : -1;
 }
@@ -361,6 +371,7 @@ k_sort_scatter(const InstDev *__restrict__ insts, InstState *__restrict__ states
     const InstState &S = states[seg >> 1];
     const int64_t ext = uni((int64_t)S.extent[seg & 1]);
     const int par = uni(S.parity);
+    const int64_t kS = uni((int64_t)S.k), E0 = uni((int64_t)S.epoch);
     const P src = make_view<P>(I, seg & 1, par);
     const P dst = make_view<P>(I, seg & 1, par ^ 1);
     const int N = I.N;
@@ -405,7 +416,10 @@ k_sort_scatter(const InstDev *__restrict__ insts, InstState *__restrict__ states
         unsigned int b0 = 0;
         if (key_run(key, len, pos) && key >= 0) b0 = atomicAdd(&cnt[key], (unsigned int)len);
         b0 = __shfl(b0, __lane_id() - pos, 64);
-        if (key >= 0) store_rec(dst, (int64_t)(gbase[key] + b0 + (unsigned int)pos), r[q]);
+        if (key >= 0) {
+          rebase_rec(r[q], E0, kS);
+          store_rec(dst, (int64_t)(gbase[key] + b0 + (unsigned int)pos), r[q]);
+        }
       }
     }
     __syncthreads();
@@ -416,7 +430,8 @@ k_sort_scatter(const InstDev *__restrict__ insts, InstState *__restrict__ states
   }
 }
 
-// Switch every sorted instance to the new buffer.
+// Switch every sorted instance to the new buffer, whose hot words count from
+// the current step.
 __global__ void __launch_bounds__(256)
 k_sort_finish(const InstDev *__restrict__ insts, InstState *__restrict__ states, int n_inst) {
   for (int i = threadIdx.x; i < n_inst; i += blockDim.x) {
@@ -428,6 +443,7 @@ k_sort_finish(const InstDev *__restrict__ insts, InstState *__restrict__ states,
       S.n_live[s] = S.sort_live[s];
     }
     S.parity ^= 1;
+    S.epoch = S.k;
   }
 }
 
