@@ -199,10 +199,11 @@ typedef struct pic_tuning {
                              launches (default: measured faster here)                */
   int32_t inline_drain;   /* where the fused pass's queued particles are drained: 0 =
                              chosen by size (default): in the particle kernel itself
-                             when the context's discharges start with at most 4 M
-                             particles in all (their steps are launch-bound), else
-                             by a drain kernel; 1 = always inline; 2 = never.  The
-                             results are the same either way.                        */
+                             when the context holds at most 4 discharges that start
+                             with at most 4 M particles in all (their steps are
+                             launch-bound), else by a drain kernel; 1 = always
+                             inline; 2 = never.  The results are the same either
+                             way.                                                    */
 } pic_tuning;
 
 /* Kernel timing (pic_kernel_times).  Durations in milliseconds summed over the

@@ -10,10 +10,15 @@ enum Mode : int { M_DEPOSIT = 0, M_PUSH = 1, M_MCC = 2, M_FUSED = 3, M_PULLBACK 
 // launch_particles only: the fused pass whose wavefronts drain their own
 // queued particles (256-thread workgroups; no k_drain launch follows).
 constexpr int M_FUSED_INLINE = 8;
-// Contexts whose discharges start with at most this many particles in all
-// take the inline drain by default: their steps are bound by launch
-// latency, not by HBM.
+// Contexts of at most kInlineDrainMaxDischarges discharges that start with
+// at most kInlineDrainMaxSlots particles in all take the inline drain by
+// default: their steps are bound by launch latency, not by HBM.  With more
+// discharges every segment's end drains a few entries per wavefront, and the
+// drain kernel wins (FP32, per step: one resolved discharge 42.5 us inline
+// against 48.6, four 75 against 79, seven 99 against 72; sixteen small
+// served requests 109 against 66).
 constexpr int64_t kInlineDrainMaxSlots = 4 << 20;
+constexpr int kInlineDrainMaxDischarges = 4;
 
 // Particles per thread of a particle-kernel tile (a tile is block x this),
 // and the tile of the drain and of the sort scatter, in particles or entries.
