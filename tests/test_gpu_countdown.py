@@ -81,3 +81,55 @@ def test_countdown_across_its_range(gpu):
     assert ref.mcc[0].candidates == int(((kn >= k1) & (kn < k1 + 20)).sum())
     ctx.close()
     ctx2.close()
+
+
+def test_split_calls_re_express_like_pic_step(gpu):
+    """With no configured sort, pic_step and the split calls (pic_deposit,
+    pic_poisson, pic_gather_push, pic_mcc) both re-express the candidacy
+    offsets after 16384 steps (a forced sort): the two runs end bitwise
+    equal by id, every candidacy before the end happened once, and the
+    others, near and far, decode to the steps they were given."""
+    from paper_2308_13092_amd import Context
+    n_steps = 16384 + 30
+    reps = 16
+    offsets = [0, 1, 100, 16383, 16384, 16385, n_steps - 1, n_steps, n_steps + 5, CNT_MAX - 1, CNT_MAX,
+               CNT_MAX + 16384, CNT_MAX + 16390, 2 * CNT_MAX + 3]
+    kn = np.array([K0 + o for o in offsets] * reps + [INT32_MAX] * reps, dtype=np.int64)
+    n = len(kn)
+    cfg = inputs.small_discharge(n_cells=16, bc=1, gap_m=0.004, n_species=1, precision=1,
+                                 n_per_species=n, p_pa=1e-6, v_rf=0.0, gamma_see=0.0,
+                                 sort_interval=0, te_ev=1.0)
+    st = inputs.particles_fp32(n, 16, 4.0e5, seed=78)
+    st["knext"] = kn
+    note("split calls re-express", n, "particles", n_steps, "steps")
+    ctxs = []
+    for _ in range(2):
+        c = Context([cfg])
+        c.set_state(0, 0, st)
+        c.set_step(0, K0)
+        ctxs.append(c)
+    a, b = ctxs
+    a.step(n_steps)
+    for _ in range(n_steps):
+        b.deposit()
+        b.poisson()
+        b.gather_push()
+        b.mcc()
+    k1 = K0 + n_steps
+    os_ = np.argsort(st["id"])
+    due = kn[os_] < k1
+    for c in (a, b):
+        d = c.diagnostics()
+        assert d["step"] == k1
+        assert d["candidates"][0] == int(due.sum())
+        g = c.get_state(0, 0)
+        o = np.argsort(g["id"])
+        kept = g["knext"][o].astype(np.int64)
+        assert np.array_equal(kept[~due], kn[os_][~due])
+        assert np.all(kept[due] >= k1)
+    ga, gb = a.get_state(0, 0), b.get_state(0, 0)
+    oa, ob = np.argsort(ga["id"]), np.argsort(gb["id"])
+    for key in ga:
+        assert np.array_equal(ga[key][oa], gb[key][ob]), key
+    a.close()
+    b.close()
