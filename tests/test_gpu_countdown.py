@@ -1,13 +1,14 @@
-"""The FP32 form's collision countdown (a 16-bit count of steps in each
-particle's hot word, with the far flag and the knext array for candidacies
-beyond its range) against the oracle's absolute candidate steps.
+"""The FP32 form's collision candidacy (a 16-bit offset from the slot's
+epoch step in each particle's hot word, with the far flag and the knext array
+for candidacies beyond its range or overdue) against the oracle's absolute
+candidate steps.
 
 A periodic electron box at very low pressure (waits of ~1e8 steps) is set to
-candidacies spread around the count's range, set_step moves it to k0, it is
-advanced 2^16 - 9 steps on the GPU, and then the oracle and the GPU advance
-together across the step where the far countdowns run out: every candidacy
-happens at its step, every far particle keeps its candidacy (false alarms are
-not candidates), and the state matches the oracle's by id.
+candidacies spread around the offset's range, set_step moves it to k0, it is
+advanced 2^16 - 9 steps on the GPU with no configured sort (the epoch is
+re-expressed by the sorts forced every 16384 steps), and then the oracle and
+the GPU advance together: every candidacy happens at its step, every far
+particle keeps its candidacy, and the state matches the oracle's by id.
 """
 import sys
 
@@ -63,7 +64,7 @@ def test_countdown_across_its_range(gpu):
     assert np.array_equal(kept[~due], kn[os_][~due])
     assert np.all(kept[due] >= k1)
     note("at", k1, "candidates", int(d["candidates"][0]))
-    # the oracle and the GPU across k0 + 2^16 - 1 (where far countdowns end)
+    # the oracle and the GPU together from there
     ref = oracle_from_states(cfg, [g1], k1)
     ctx2 = Context([cfg])
     ctx2.set_state(0, 0, g1)
