@@ -91,9 +91,9 @@ typedef struct pic_config {
   double gamma_see;       /* secondary electrons per absorbed ion (probability)        */
   double t_see_ev;        /* secondary-electron temperature; 0 -> 2 eV                 */
   uint64_t seed;          /* Philox key material for this discharge                    */
-  int32_t sort_interval;  /* steps between cell sorts; 0 -> none beyond the one every
-                             16384 steps that the FP32 state needs (context-wide:
-                             the value of the first active instance is used)      */
+  int32_t sort_interval;  /* steps between cell sorts; 0 -> none (FP32 state: none
+                             beyond the one it needs every 16384 steps; context-
+                             wide: the value of the first active instance is used) */
   int32_t n_species;      /* 2 = electrons + Ar+; 1 = electrons only on a fixed
                              neutralising ion background (periodic only)             */
   int32_t collisions;     /* 1 = Monte-Carlo collisions on; 0 = off                    */
@@ -252,15 +252,17 @@ pic_status pic_poisson(pic_ctx *ctx);
 pic_status pic_gather_push(pic_ctx *ctx);
 
 /* Step 6: null-collision Monte-Carlo collisions on v^{k+1/2} (creates
- * ionisation pairs), then k <- k + 1.  Every 16384th call without a sort in
- * between ends with pic_sort (the FP32 state's candidacy offsets need it). */
+ * ionisation pairs), then k <- k + 1.  In the FP32 state form, every 16384th
+ * call without a sort in between ends with pic_sort (the candidacy offsets
+ * need it). */
 pic_status pic_mcc(pic_ctx *ctx);
 
 /* n full steps.  Each step is one field kernel plus one fused particle pass
  * (gather, push, boundaries, collisions and the deposit of x^{k+1}); every
- * sort_interval steps the particles are sorted by cell and compacted (and at
- * least every 16384 steps: the FP32 hot word stores each particle's next
- * collision candidacy as an offset from the step of the last sort).  The
+ * sort_interval steps the particles are sorted by cell and compacted (in the
+ * FP32 state form at least every 16384 steps: its hot word stores each
+ * particle's next collision candidacy as an offset from the step of the last
+ * sort).  The
  * result is the same particle set as pic_deposit, pic_poisson,
  * pic_gather_push, pic_mcc called in turn. */
 pic_status pic_step(pic_ctx *ctx, int32_t n_steps);

@@ -262,8 +262,8 @@ struct pic_ctx {
   int rebalance_every = 0;     // pic_step rebalances every this many steps (0 = never)
   int64_t host_step = 0;
   // steps since the last sort of every slot (each sort moves the FP32 hot
-  // words' epoch to the current step; pic_step and pic_mcc force one before
-  // this reaches kRebaseSteps)
+  // words' epoch to the current step; in the FP32 form pic_step and pic_mcc
+  // force one before this reaches kRebaseSteps)
   int64_t since_rebase = 0;
   bool deposit_current = false;
   std::string err;
@@ -983,7 +983,7 @@ pic_status pic_mcc(pic_ctx *c) {
   HIP_TRY(c, launch_drain(c->d_inst, c->d_state, c->n_inst, c->prec, M_MCC, drain_grid(c, M_MCC), true, c->stream));
   c->deposit_current = false;
   c->host_step++;
-  if (++c->since_rebase >= kRebaseSteps) return pic_sort(c);
+  if (++c->since_rebase >= kRebaseSteps && c->prec == PIC_FP32_STATE) return pic_sort(c);
   return PIC_OK;
 }
 
@@ -1042,9 +1042,10 @@ pic_status pic_step(pic_ctx *c, int32_t n_steps) {
   bool open = false;
   const int R = c->rebalance_every;
   for (int n = 0; n < n_steps; ++n) {
-    // a sort at its interval, or one that keeps the hot words' epoch offsets
-    // in range (see kRebaseSteps)
-    const bool sort = (S > 0 && ((c->host_step + 1) % S) == 0) || c->since_rebase + 1 >= kRebaseSteps;
+    // a sort at its interval, or (FP32 form) one that keeps the hot words'
+    // epoch offsets in range (see kRebaseSteps)
+    const bool sort = (S > 0 && ((c->host_step + 1) % S) == 0) ||
+                      (c->prec == PIC_FP32_STATE && c->since_rebase + 1 >= kRebaseSteps);
     const bool rebal = R > 0 && ((c->host_step + 1) % R) == 0;
     if (c->timing || !c->tune.use_graph) {
       const bool leave_open = !sort && !rebal && n + 1 < n_steps;
