@@ -110,3 +110,34 @@ def test_checkpoint_of_another_configuration_is_refused(gpu):
     assert np.array_equal(np.sort(before["id"]), np.sort(after["id"]))
     a.close()
     b.close()
+
+
+def test_resume_across_the_forced_re_expression(gpu):
+    """FP32 state with no configured sort: the checkpoint is taken 4 steps
+    before the sort that re-expresses the candidacy offsets (after 16384
+    steps) and restored into a fresh context, whose own forced sort comes
+    16384 steps later; both runs end bit for bit alike.  A periodic electron
+    box below the ionisation threshold keeps its extent without sorts."""
+    from paper_2308_13092_amd import Context
+    cfg = inputs.small_discharge(n_cells=16, bc=1, gap_m=0.004, n_species=1, precision=1,
+                                 n_per_species=8_000, p_pa=0.05, v_rf=0.0, gamma_see=0.0,
+                                 sort_interval=0, te_ev=1.0, seed=43)
+    note("checkpoint across the forced re-expression")
+    a = Context([cfg])
+    a.step(16380)
+    ck = a.checkpoint(0)
+    a.step(12)
+    b = Context([cfg])
+    b.restore(0, ck)
+    b.step(12)
+    da, db = a.diagnostics(0), b.diagnostics(0)
+    for key in ("step", "status", "n_live", "deposit_total", "kinetic_j_m2", "field_j_m2", "candidates",
+                "elastic", "excitations", "ionisations", "particle_steps"):
+        assert np.array_equal(np.asarray(da[key]), np.asarray(db[key])), key
+    assert da["step"] == 16392 and da["candidates"][0] > 1000 and da["status"] == 0
+    ga, gb = a.get_state(0, 0), b.get_state(0, 0)
+    oa, ob = np.argsort(ga["id"]), np.argsort(gb["id"])
+    for key in ga:
+        assert np.array_equal(ga[key][oa], gb[key][ob]), key
+    a.close()
+    b.close()
