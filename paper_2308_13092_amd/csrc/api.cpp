@@ -254,6 +254,7 @@ struct pic_ctx {
   unsigned long long *d_diag = nullptr;
   int max_n = 2;
   int field_classes = 0;   // field_class bits of the used slots
+  int n_used = 0;          // used slots
   bool inline_drain = false;   // fused passes drain in the particle kernel (small contexts)
   // 1024 threads per block: measured fastest on the large workload.  Plain
   // launches: on every workload measured they beat graph replay (by about
@@ -325,8 +326,10 @@ static void choose_drain(pic_ctx *c) {
 static void recompute_max_n(pic_ctx *c) {
   int m = 2;
   c->field_classes = 0;
+  c->n_used = 0;
   for (auto &s : c->slots)
     if (s.used) {
+      ++c->n_used;
       m = std::max(m, (int)s.cfg.n_cells);
       c->field_classes |= field_class((int)s.cfg.n_cells);
     }
@@ -366,7 +369,14 @@ static int particle_grid(const pic_ctx *c, int block) {
 // The sort's chains (load, LDS rank, scattered stores) are latency bound:
 // more workgroups than stay resident at once measured faster (per CU 4 / 8 /
 // 16: sweep 3.31 / 3.16 / 3.00 ms per sort, large 1.077 / 1.056 / 1.044).
-static int sort_grid(const pic_ctx *c) { return capped(c, (int64_t)c->n_cu * 16, kSortTile); }
+// Finer still (64, 128) the sorts kept shrinking (sweep 2.76, 2.68 ms), but
+// a single large discharge's next streaming passes slowed by as much (each
+// cell's particles come from more pieces, in a less regular order): a batch
+// of more than four discharges sorts with 128 per CU, a context of a few
+// with 16.
+static int sort_grid(const pic_ctx *c) {
+  return capped(c, (int64_t)c->n_cu * (c->n_used > 4 ? 128 : 16), kSortTile);
+}
 // The persistent moments pass: four workgroups per CU.
 static int moments_grid(const pic_ctx *c) { return capped(c, (int64_t)c->n_cu * 4, kSortTile); }
 // The drain grid: four times the workgroups resident at once.  The queue's
