@@ -385,8 +385,10 @@ static int moments_grid(const pic_ctx *c) { return capped(c, (int64_t)c->n_cu * 
 // 4 / 8 / 16: sweep drain 0.279 / 0.278 / 0.261 / 0.255 / 0.283 ms, large
 // 42.4 / 44.0 / 42.8 / 47.5 / 56.5 us: small queues pay the per-workgroup
 // set-up).
+// A batch of more than four discharges (long queues over many segments)
+// takes eight times.
 static int drain_grid(const pic_ctx *c, int mode) {
-  return capped(c, (int64_t)c->n_cu * c->drain_per_cu[mode] * 4, kDrainTile);
+  return capped(c, (int64_t)c->n_cu * c->drain_per_cu[mode] * (c->n_used > 4 ? 8 : 4), kDrainTile);
 }
 
 // Fill InstDev for slot i from its config and block offset; write host arrays.
