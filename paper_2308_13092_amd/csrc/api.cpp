@@ -254,7 +254,9 @@ struct pic_ctx {
   unsigned long long *d_diag = nullptr;
   int max_n = 2;
   int field_classes = 0;   // field_class bits of the used slots
-  int n_used = 0;          // used slots
+  // more than four discharges that start with at least kBatchGridSlots
+  // particles in all: the sort and drain grids are larger (see sort_grid)
+  bool batch_grids = false;
   bool inline_drain = false;   // fused passes drain in the particle kernel (small contexts)
   // 1024 threads per block: measured fastest on the large workload.  Plain
   // launches: on every workload measured they beat graph replay (by about
@@ -318,6 +320,7 @@ static void choose_drain(pic_ctx *c) {
     }
   const bool small = used <= kInlineDrainMaxDischarges && total <= kInlineDrainMaxSlots;
   c->inline_drain = c->tune.inline_drain == 1 || (c->tune.inline_drain == 0 && small);
+  c->batch_grids = used > 4 && total >= kBatchGridSlots;
 }
 
 // Called whenever the set of slots changes: the grid bound and the grid
@@ -326,10 +329,8 @@ static void choose_drain(pic_ctx *c) {
 static void recompute_max_n(pic_ctx *c) {
   int m = 2;
   c->field_classes = 0;
-  c->n_used = 0;
   for (auto &s : c->slots)
     if (s.used) {
-      ++c->n_used;
       m = std::max(m, (int)s.cfg.n_cells);
       c->field_classes |= field_class((int)s.cfg.n_cells);
     }
@@ -371,11 +372,13 @@ static int particle_grid(const pic_ctx *c, int block) {
 // 16: sweep 3.31 / 3.16 / 3.00 ms per sort, large 1.077 / 1.056 / 1.044).
 // Finer still (64, 128) the sorts kept shrinking (sweep 2.76, 2.68 ms), but
 // a single large discharge's next streaming passes slowed by as much (each
-// cell's particles come from more pieces, in a less regular order): a batch
-// of more than four discharges sorts with 128 per CU, a context of a few
-// with 16.
+// cell's particles come from more pieces, in a less regular order): a large
+// batch (batch_grids) sorts with 128 per CU, other contexts with 16.  A
+// batch of many small discharges pays each extra workgroup's set-up (a
+// prefix over every segment): the served trace of small requests got slower
+// with the larger grids (p50 0.70 -> 0.83 s).
 static int sort_grid(const pic_ctx *c) {
-  return capped(c, (int64_t)c->n_cu * (c->n_used > 4 ? 128 : 16), kSortTile);
+  return capped(c, (int64_t)c->n_cu * (c->batch_grids ? 128 : 16), kSortTile);
 }
 // The persistent moments pass: four workgroups per CU.
 static int moments_grid(const pic_ctx *c) { return capped(c, (int64_t)c->n_cu * 4, kSortTile); }
@@ -385,10 +388,10 @@ static int moments_grid(const pic_ctx *c) { return capped(c, (int64_t)c->n_cu * 
 // 4 / 8 / 16: sweep drain 0.279 / 0.278 / 0.261 / 0.255 / 0.283 ms, large
 // 42.4 / 44.0 / 42.8 / 47.5 / 56.5 us: small queues pay the per-workgroup
 // set-up).
-// A batch of more than four discharges (long queues over many segments)
-// takes eight times.
+// A large batch (batch_grids: long queues over many segments) takes eight
+// times.
 static int drain_grid(const pic_ctx *c, int mode) {
-  return capped(c, (int64_t)c->n_cu * c->drain_per_cu[mode] * (c->n_used > 4 ? 8 : 4), kDrainTile);
+  return capped(c, (int64_t)c->n_cu * c->drain_per_cu[mode] * (c->batch_grids ? 8 : 4), kDrainTile);
 }
 
 // Fill InstDev for slot i from its config and block offset; write host arrays.

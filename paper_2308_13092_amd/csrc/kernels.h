@@ -19,6 +19,10 @@ constexpr int M_FUSED_INLINE = 8;
 // served requests 109 against 66).
 constexpr int64_t kInlineDrainMaxSlots = 4 << 20;
 constexpr int kInlineDrainMaxDischarges = 4;
+// Contexts of more than four discharges that start with at least this many
+// particles in all sort and drain with larger grids (measured: the batched
+// sweep of 1.25e8 particles gains, a served trace of a few million loses).
+constexpr int64_t kBatchGridSlots = 32 << 20;
 
 // Particles per thread of a particle-kernel tile (a tile is block x this),
 // and the tile of the drain and of the sort scatter, in particles or entries.
