@@ -355,8 +355,10 @@ pic_status pic_impacts(pic_ctx *ctx, int32_t inst, int32_t species, int32_t wall
  * (PIC_EINVAL if smaller; synchronises); pic_checkpoint_load restores it into
  * slot inst of any context whose configuration of that slot is the same (grid,
  * drive, gas, weight, time step, capacity, averaging, seed, state form;
- * PIC_EINVAL if not, with the slot unchanged).  The buffer is the caller's;
- * its layout is this library version's own. */
+ * PIC_EINVAL if not, with the slot unchanged; in the FP32 state form the
+ * restored particles' collision candidacies are re-expressed from the
+ * restored step).  The buffer is the caller's; its layout is this library
+ * version's own (a checkpoint of another version is refused with PIC_EINVAL). */
 pic_status pic_checkpoint_bytes(pic_ctx *ctx, int32_t inst, size_t *bytes);
 pic_status pic_checkpoint_save(pic_ctx *ctx, int32_t inst, void *buf, size_t bytes);
 pic_status pic_checkpoint_load(pic_ctx *ctx, int32_t inst, const void *buf, size_t bytes);
