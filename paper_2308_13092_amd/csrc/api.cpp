@@ -380,6 +380,10 @@ static int particle_grid(const pic_ctx *c, int block) {
 static int sort_grid(const pic_ctx *c) {
   return capped(c, (int64_t)c->n_cu * (c->batch_grids ? 128 : 16), kSortTile);
 }
+// The sort's count keeps 16 per CU: each workgroup clears and flushes a
+// histogram of the grid's cells, which the large batch grid multiplied
+// (sweep count 136 us at 16 per CU, 234 us at 128).
+static int count_grid(const pic_ctx *c) { return capped(c, (int64_t)c->n_cu * 16, kSortTile); }
 // The persistent moments pass: four workgroups per CU.
 static int moments_grid(const pic_ctx *c) { return capped(c, (int64_t)c->n_cu * 4, kSortTile); }
 // The drain grid: four times the workgroups resident at once.  The queue's
@@ -615,7 +619,7 @@ static pic_status deposit_only(pic_ctx *c, int only) {
   // order, as every later sort does, so the first steps stream sorted state
   // (on the large discharge the first sort of an unsorted load takes about
   // five times as long as the later ones).
-  HIP_TRY(c, launch_sort(c->d_inst, c->d_state, c->n_inst, c->prec, sort_grid(c), c->max_n, st));
+  HIP_TRY(c, launch_sort(c->d_inst, c->d_state, c->n_inst, c->prec, sort_grid(c), count_grid(c), c->max_n, st));
   launch_zero_deposit(c->d_inst, c->d_state, c->n_inst, st);
   HIP_TRY(c, launch_particles(c->d_inst, c->d_state, c->n_inst, c->prec, M_DEPOSIT, 256,
                               particle_grid(c, 256), c->max_n, st));
@@ -740,7 +744,7 @@ static pic_status enqueue_step(pic_ctx *c, hipStream_t st, bool sort, bool timed
   if (all) { pic_status r = ev_end(c); if (r) return r; }
   if (sort) {
     if (timed) { pic_status r = ev_begin(c, 2); if (r) return r; }
-    HIP_TRY(c, launch_sort(c->d_inst, c->d_state, c->n_inst, c->prec, sort_grid(c), c->max_n, st));
+    HIP_TRY(c, launch_sort(c->d_inst, c->d_state, c->n_inst, c->prec, sort_grid(c), count_grid(c), c->max_n, st));
     if (timed) { pic_status r = ev_end(c); if (r) return r; }
   }
   return PIC_OK;
@@ -1004,7 +1008,7 @@ pic_status pic_mcc(pic_ctx *c) {
 
 pic_status pic_sort(pic_ctx *c) {
   if (!c) return PIC_EINVAL;
-  HIP_TRY(c, launch_sort(c->d_inst, c->d_state, c->n_inst, c->prec, sort_grid(c), c->max_n, c->stream));
+  HIP_TRY(c, launch_sort(c->d_inst, c->d_state, c->n_inst, c->prec, sort_grid(c), count_grid(c), c->max_n, c->stream));
   c->since_rebase = 0;
   return PIC_OK;
 }
@@ -1015,7 +1019,7 @@ pic_status pic_rebalance(pic_ctx *c) {
   for (int i = 0; i < c->n_inst; ++i) any |= c->slots[i].used && c->host_inst[i].rb_ppc > 0;
   if (!any) return PIC_OK;
   // cell order (and the cell ranges the flags are read from)
-  HIP_TRY(c, launch_sort(c->d_inst, c->d_state, c->n_inst, c->prec, sort_grid(c), c->max_n, c->stream));
+  HIP_TRY(c, launch_sort(c->d_inst, c->d_state, c->n_inst, c->prec, sort_grid(c), count_grid(c), c->max_n, c->stream));
   for (int i = 0; i < c->n_inst; ++i) {
     if (!c->slots[i].used || c->host_inst[i].rb_ppc <= 0) continue;
     InstState S;
@@ -1027,7 +1031,7 @@ pic_status pic_rebalance(pic_ctx *c) {
     if (e != hipSuccess) return fail(c, PIC_EDEVICE, std::string("rebalance: ") + hipGetErrorString(e));
   }
   // compact: the merged-away particles leave, the split children join the order
-  HIP_TRY(c, launch_sort(c->d_inst, c->d_state, c->n_inst, c->prec, sort_grid(c), c->max_n, c->stream));
+  HIP_TRY(c, launch_sort(c->d_inst, c->d_state, c->n_inst, c->prec, sort_grid(c), count_grid(c), c->max_n, c->stream));
   c->since_rebase = 0;
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->deposit_current = false;

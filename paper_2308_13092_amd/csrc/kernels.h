@@ -55,8 +55,9 @@ hipError_t launch_drain(const InstDev *insts, InstState *states, int n_inst, int
 int drain_blocks_per_cu(int prec, int mode);
 // The closing kernel of a fused pass alone (after an inline-drained pass).
 void launch_finalize(const InstDev *insts, InstState *states, int n_inst, hipStream_t s);
+// grid: workgroups of the scatter; count_grid: of the count.
 hipError_t launch_sort(const InstDev *insts, InstState *states, int n_inst, int prec, int grid,
-                       int max_n, hipStream_t s);
+                       int count_grid, int max_n, hipStream_t s);
 void launch_diag(const InstDev *insts, InstState *states, int inst, int prec, int64_t max_particles,
                  unsigned long long *out, hipStream_t s);
 void launch_zero_deposit(const InstDev *insts, InstState *states, int n_inst, hipStream_t s);

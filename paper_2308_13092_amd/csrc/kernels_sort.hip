@@ -452,14 +452,14 @@ size_t sort_lds_bytes(int max_n, int prec) {
 }
 
 hipError_t launch_sort(const InstDev *insts, InstState *states, int n_inst, int prec, int grid,
-                       int max_n, hipStream_t s) {
+                       int count_grid, int max_n, hipStream_t s) {
   const size_t lds = sort_lds_bytes(max_n, prec);
   // The count needs only the histogram (and, FP64, the nodes to locate x).
   const size_t lds_count = 4 * (size_t)((max_n + 2) & ~1) + (prec == 0 ? 8 * (size_t)(max_n + 1) : 0);
   if (prec == 1)
-    hipLaunchKernelGGL(k_sort_count<P32>, dim3(grid), dim3(kSB), lds_count, s, insts, states, n_inst, max_n);
+    hipLaunchKernelGGL(k_sort_count<P32>, dim3(count_grid), dim3(kSB), lds_count, s, insts, states, n_inst, max_n);
   else
-    hipLaunchKernelGGL(k_sort_count<P64>, dim3(grid), dim3(kSB), lds_count, s, insts, states, n_inst, max_n);
+    hipLaunchKernelGGL(k_sort_count<P64>, dim3(count_grid), dim3(kSB), lds_count, s, insts, states, n_inst, max_n);
   hipLaunchKernelGGL(k_sort_scan, dim3(n_inst), dim3(kSB), 0, s, insts, states);
   if (prec == 1)
     hipLaunchKernelGGL(k_sort_scatter<P32>, dim3(grid), dim3(kSB), lds, s, insts, states, n_inst, max_n);
