@@ -84,6 +84,29 @@ def assert_same_instance(a, ia, b, ib, nsp=2):
         assert np.array_equal(fa[k], fb[k]), (ia, k)
 
 
+def test_large_batch_equals_alone(gpu):
+    """Six discharges scaled to 35 M particles in all: the batch sorts and
+    drains with the large-batch grids (a sort scatter of 128 workgroups per
+    CU beside a count of 16, a drain of eight times the resident
+    workgroups), each discharge alone with the ordinary ones.  A sort falls
+    inside the 12 steps; every discharge ends bitwise as it does alone."""
+    cfgs = mixed_configs(1, n_scale=320.0)
+    total = sum(2 * c["n_per_species"] for c in cfgs if c["n_cells"] > 0)
+    note("large batch vs alone", total, [c["n_per_species"] for c in cfgs])
+    assert total >= 32 << 20
+    steps = 12
+    batch = Context()(cfgs)
+    batch.step(steps)
+    for i, cfg in enumerate(cfgs):
+        if cfg["n_cells"] == 0:
+            continue
+        alone = Context()([cfg])
+        alone.step(steps)
+        assert_same_instance(batch, i, alone, 0)
+        alone.close()
+    batch.close()
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_batch_equals_alone(gpu, prec):
     cfgs = mixed_configs(prec)
